@@ -1,0 +1,24 @@
+"""Compile the oracle's C code into ``oracle/liboracle.so`` with gcc.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).  Building the checker
+is not using it: the package's ``build()`` calls this so the tests find it.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "jq_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+                               "-D_DEFAULT_SOURCE", "-Wall", "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build())
