@@ -1,0 +1,305 @@
+/*
+ * jq - state-vector gate application on one MI355X (gfx950).
+ *
+ * The operations follow De Raedt et al., "Massively parallel quantum computer
+ * simulator, eleven years later" (Comput. Phys. Commun.):
+ *
+ *  - the state of N qubits is a vector of 2^N complex amplitudes (Sec. 2,
+ *    Eq. STAT2); qubit j is bit j of the basis index, qubit 0 the least
+ *    significant bit;
+ *  - a circuit is a sequence of unitary operations on that vector (Sec. 2);
+ *    a single-qubit gate updates 2^(N-1) amplitude pairs in place (Eq. NUM2),
+ *    a two-qubit gate 2^(N-2) groups of four (Sec. 2);
+ *  - outputs are the amplitudes and the outcome probabilities of qubits
+ *    (Sec. 2, last paragraph);
+ *  - three encodings: complex128 (the E flavour, 16 B per amplitude, Sec. 1),
+ *    complex64 (8 B), and the adaptive two-byte polar code of Sec. 4.1.
+ *
+ * Conventions that hold for every call:
+ *  - Every call returns an int: JQ_OK (0) or a negative error code, and on
+ *    error jq_last_error() (thread-local) describes it.  Arguments are
+ *    checked on the host before anything is enqueued; on an argument error
+ *    the state is unchanged.  A device fault surfaces as JQ_EDEVICE at the
+ *    next call that synchronises.
+ *  - Pointers named "host" below are host memory owned by the caller and
+ *    only read or written during the call.  Device memory of a state is
+ *    owned by the library (allocated through the registered allocator, see
+ *    jq_set_allocator, else hipMalloc) and freed by jq_state_destroy.
+ *  - Calls that only enqueue work are asynchronous on the state's stream;
+ *    calls that return data (norm, probabilities, read) synchronise it.
+ *  - Complex numbers on the host are interleaved (re, im) doubles.
+ *  - Matrices are row-major; for a two-qubit gate the first listed qubit is
+ *    the most significant bit of the row/column index, the basis
+ *    |control,target> that App. A uses for CNOT and U(k).  Outputs of
+ *    jq_probabilities use the opposite, state-like order: bit m of the
+ *    output index is the value of qubits[m].
+ *  - A jq_state must not be used from two threads at once.
+ */
+#ifndef JQ_H
+#define JQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define JQ_OK 0
+#define JQ_EINVAL (-1)       /* invalid argument */
+#define JQ_ENOMEM (-2)       /* not enough device (HBM) memory */
+#define JQ_EDEVICE (-3)      /* HIP runtime error or device fault */
+#define JQ_EUNSUPPORTED (-4) /* valid request this build does not implement */
+#define JQ_EZERO (-5)        /* projection onto a zero-probability outcome */
+#define JQ_EBUSY (-6)        /* server queue full (non-blocking submit) */
+
+#define JQ_MAX_QUBITS 63
+#define JQ_MAX_CONTROLS 4
+
+/* Amplitude encodings (Sec. 1: E = complex128; Sec. 4.1: the two-byte
+ * code, stored as two int8 planes b0[2^N] then b1[2^N] plus the FP64
+ * range (r0, r1) in device memory). */
+typedef enum { JQ_C128 = 0, JQ_C64 = 1, JQ_COMPACT = 2 } jq_encoding;
+
+/* Initial states: |0...0> (Sec. 2), the uniform superposition 2^(-N/2)
+ * (Sec. 5.1), or a basis state |basis>. */
+typedef enum { JQ_INIT_ZERO = 0, JQ_INIT_UNIFORM = 1, JQ_INIT_BASIS = 2 } jq_init;
+
+/* Gate classes.  DENSE: a full 2^nq x 2^nq matrix.  DIAGONAL: only the
+ * 2^nq diagonal entries are given.  PERM_X: the bit flip X of App. A on one
+ * target (with controls this is CNOT or TOFFOLI); no matrix. */
+typedef enum { JQ_DENSE = 0, JQ_DIAGONAL = 1, JQ_PERM_X = 2 } jq_gate_kind;
+
+/* Quantisation of the two-byte code.  PER_GATE decodes and re-encodes the
+ * state around every gate, recomputing (r0, r1) each time (Sec. 4.1 as the
+ * paper runs it).  PER_BLOCK does so once per fused block of gates. */
+typedef enum { JQ_COMPACT_PER_GATE = 0, JQ_COMPACT_PER_BLOCK = 1 } jq_compact_mode;
+
+/* One gate.  qubits[0..nq-1] are the targets (nq = 1 or 2; nq = 1 for
+ * PERM_X), controls[0..nc-1] the controls (all must be 1 for the gate to
+ * act).  m holds the matrix: 2^nq x 2^nq row-major complex for DENSE, the
+ * 2^nq diagonal entries for DIAGONAL, unused for PERM_X.  All qubits of a
+ * gate must be distinct and in [0, N). */
+typedef struct {
+    int32_t kind;
+    int32_t nq;
+    int32_t nc;
+    int32_t qubits[2];
+    int32_t controls[JQ_MAX_CONTROLS];
+    int32_t pad_;
+    double m[32];
+} jq_gate;
+
+/* Execution options for jq_apply_circuit (NULL = defaults).
+ *  fusion:      0 = let the planner fuse gates into register-blocked tile
+ *               passes with its tuned width; 1 = one kernel per gate;
+ *               k >= 2 = fuse with at most k register qubits per pass.
+ *  compact_mode: a jq_compact_mode, used for JQ_COMPACT states.
+ *  max_ops:     upper bound on gates per fused pass (0 = default). */
+typedef struct {
+    int32_t fusion;
+    int32_t compact_mode;
+    int32_t max_ops;
+    int32_t reserved[5];
+} jq_exec_opts;
+
+typedef struct jq_state jq_state;
+
+/* ---- state lifetime -------------------------------------------------- */
+
+/* Create an N-qubit state (1 <= N <= JQ_MAX_QUBITS; App. A, QUBITS) in the
+ * given encoding on the current HIP device, initialised to |0...0>.
+ * 2^N * bytes-per-amplitude (16, 8, 2) must fit in free device memory, else
+ * JQ_ENOMEM.  *out receives the handle. */
+int jq_state_create(int n_qubits, jq_encoding enc, jq_state **out);
+
+/* Free the state's device memory; the handle is invalid afterwards. */
+int jq_state_destroy(jq_state *s);
+
+/* Set the state to |0...0>, the uniform superposition, or |basis>
+ * (basis < 2^N).  Asynchronous. */
+int jq_state_init(jq_state *s, jq_init mode, uint64_t basis);
+
+/* Number of qubits, encoding, and device bytes held (host outputs; any may
+ * be NULL). */
+int jq_state_info(const jq_state *s, int *n_qubits, int *encoding, uint64_t *bytes);
+
+/* Device address of the amplitude storage (for c128/c64: 2^N interleaved
+ * complex values; for compact: the b0 plane followed by the b1 plane). */
+int jq_state_device_ptr(const jq_state *s, void **ptr);
+
+/* Run the state's work on this hipStream_t (NULL = the library's own
+ * stream).  The stream must outlive its use by the state. */
+int jq_set_stream(jq_state *s, void *hip_stream);
+
+/* Wait until all work enqueued for the state has finished. */
+int jq_synchronize(jq_state *s);
+
+/* Route state allocations through alloc(bytes, ctx) / release(ptr, ctx)
+ * (for example a framework's caching allocator).  Both NULL restores
+ * hipMalloc/hipFree.  States keep the functions they were created with. */
+int jq_set_allocator(void *(*alloc)(size_t, void *), void (*release)(void *, void *), void *ctx);
+
+/* ---- gates ----------------------------------------------------------- */
+
+/* Lower a named instruction of App. A into a jq_gate (host only, no
+ * device work).  Names: I H X Y Z S S+ T T+ U1 U2 U3 +X -X +Y -Y R CNOT U
+ * TOFFOLI, plus RZ (diag(e^{-i t/2}, e^{i t/2})), CZ (= U with k=1),
+ * CP (diag(1,1,1,e^{i phi})), SWAP, MAT1 (8 params: explicit 2x2) and
+ * MAT2 (32 params: explicit 4x4).  qubits as in App. A's syntax (controls
+ * first); params are the angles or k of App. A.  Returns JQ_EINVAL on an
+ * unknown name or wrong argument count.  "I" lowers to an empty gate
+ * (nq = 0) that jq_apply_circuit skips. */
+int jq_gate_named(const char *name, const int *qubits, int nq, const double *params, int np, jq_gate *out);
+
+/* Apply one gate (Sec. 2, Eq. NUM2 and its four-amplitude analogue).
+ * matrix is copied before return.  JQ_EINVAL if the qubits are invalid or
+ * the matrix does not fit the kind (e.g. a non-zero off-diagonal entry for
+ * DIAGONAL).  Asynchronous. */
+int jq_apply_gate(jq_state *s, int kind, const int *qubits, int nq, const int *controls, int nc,
+                  const double *matrix);
+
+/* Apply gates[0..count-1] in order.  All gates are validated first; on an
+ * invalid gate nothing is applied.  Gates may be fused into tile passes
+ * (see jq_exec_opts); the result equals applying them one by one up to
+ * floating-point rounding.  Asynchronous. */
+int jq_apply_circuit(jq_state *s, const jq_gate *gates, size_t count, const jq_exec_opts *opts);
+
+/* ---- reductions (FP64 whatever the encoding) ------------------------ */
+
+/* Squared norm sum |a_i|^2 (the left side of Eq. STAT1).  Synchronises. */
+int jq_norm(jq_state *s, double *out);
+
+/* Marginal distribution over qubits[0..nq-1] (distinct, 0 <= nq <= N,
+ * nq <= 30): out (host, 2^nq doubles) receives sum |a_i|^2 over the basis
+ * states whose bit qubits[m] equals bit m of the output index (Sec. 2).
+ * Deterministic summation order.  Synchronises. */
+int jq_probabilities(jq_state *s, const int *qubits, int nq, double *out);
+
+/* Expectation values <Qx(n)>, <Qy(n)>, <Qz(n)> = <(1 - sigma^alpha_n)>/2 of
+ * every qubit (App. A, BEGIN MEASUREMENT); qx, qy, qz are host arrays of N
+ * doubles (any may be NULL).  Synchronises. */
+int jq_expectations(jq_state *s, double *qx, double *qy, double *qz);
+
+/* Scale the state to unit norm, in FP64.  For the two-byte code this scales
+ * (r0, r1) and leaves the codes alone.  JQ_EZERO if the norm is zero. */
+int jq_renormalize(jq_state *s);
+
+/* ---- amplitude transfer --------------------------------------------- */
+
+/* Copy amplitudes [first, first+count) to host as complex128 (decoded for
+ * the two-byte code).  Synchronises. */
+int jq_read_amplitudes(jq_state *s, uint64_t first, uint64_t count, double *out);
+
+/* Overwrite amplitudes [first, first+count) from host complex128.  For the
+ * two-byte code only a full write (first = 0, count = 2^N) is allowed; it
+ * takes (r0, r1) from the data as the encoder does.  Synchronises. */
+int jq_write_amplitudes(jq_state *s, uint64_t first, uint64_t count, const double *in);
+
+/* Two-byte code only: copy codes [first, first+count) of both planes to
+ * host int8 arrays (either may be NULL) and the current range to range[2]
+ * (may be NULL).  Synchronises. */
+int jq_read_codes(jq_state *s, uint64_t first, uint64_t count, int8_t *b0, int8_t *b1, double *range);
+
+/* ---- per-launch timing ------------------------------------------------ */
+
+typedef struct {
+    char name[32];    /* kernel class */
+    uint64_t launches;
+    double total_ms;  /* sum of hipEvent-measured launch durations */
+    double bytes;     /* algorithmic HBM bytes of those launches */
+} jq_kernel_stat;
+
+/* Record a hipEvent pair on the state's stream around every kernel launch
+ * (on != 0) or stop (on == 0); enabling clears the counters. */
+int jq_profile_enable(jq_state *s, int on);
+
+/* Synchronise and report per-class totals; writes up to max entries and
+ * the number of classes to *count. */
+int jq_profile_read(jq_state *s, jq_kernel_stat *out, int max, int *count);
+
+/* ---- batched small circuits ---------------------------------------- */
+
+/* A circuit for batch or serving use: n_qubits and gates[0..n_gates-1]
+ * (host memory, read during the call that takes it). */
+typedef struct {
+    int32_t n_qubits;
+    int32_t pad_;
+    uint64_t n_gates;
+    const jq_gate *gates;
+} jq_circuit;
+
+typedef struct jq_batch jq_batch;
+
+/* Prepare count independent circuits (each 1 <= N <= 20) for one
+ * persistent launch: gates are lowered and packed into device memory and a
+ * packed state arena is allocated.  enc is JQ_C128 or JQ_C64.  Work runs on
+ * hip_stream (NULL = the library's stream). */
+int jq_batch_create(const jq_circuit *circuits, size_t count, jq_encoding enc, const jq_exec_opts *opts,
+                    void *hip_stream, jq_batch **out);
+
+/* Reset every state to |0...0> and run every circuit, in one kernel launch
+ * (a persistent grid that pulls circuits from a device work counter).
+ * Asynchronous; elapsed_ms (may be NULL) receives the launch's
+ * hipEvent-measured time after synchronising when non-NULL. */
+int jq_batch_run(jq_batch *b, double *elapsed_ms);
+
+/* Copy amplitudes of circuit `index` to host complex128.  Synchronises. */
+int jq_batch_read(jq_batch *b, size_t index, uint64_t first, uint64_t count, double *out);
+
+int jq_batch_destroy(jq_batch *b);
+
+/* ---- serving ---------------------------------------------------------- */
+
+typedef struct jq_server jq_server;
+
+typedef struct {
+    uint64_t ticket;
+    int32_t status;        /* JQ_OK or the error of that request */
+    int32_t n_qubits;
+    double norm;           /* FP64 squared norm of the final state */
+    double latency_ms;     /* submit -> device completion */
+    double queue_ms;       /* submit -> admission */
+    jq_state *state;       /* final state, resident until jq_server_release */
+} jq_result;
+
+typedef struct {
+    uint64_t submitted, completed, rejected;
+    double p50_ms, p99_ms, mean_ms;
+    double throughput_per_s; /* completions / (last completion - first submit) */
+    uint64_t peak_resident_bytes;
+} jq_server_stats;
+
+/* Start a request loop on the current device: admitted requests' states
+ * may together hold at most hbm_budget bytes; work is spread over
+ * n_streams streams; at most queue_cap requests wait for admission. */
+int jq_server_create(uint64_t hbm_budget, int n_streams, int queue_cap, jq_encoding enc, jq_server **out);
+
+/* Queue a circuit (copied).  blocking = 0 returns JQ_EBUSY when the queue
+ * is full; a request whose state alone exceeds the budget is rejected with
+ * JQ_ENOMEM.  *ticket identifies the request. */
+int jq_server_submit(jq_server *sv, const jq_circuit *c, int blocking, uint64_t *ticket);
+
+/* Wait for (timeout_ms < 0: forever) or poll (timeout_ms = 0) any finished
+ * request; JQ_EBUSY if none finished in time.  The result's state stays
+ * resident (and counts against the budget) until jq_server_release. */
+int jq_server_wait(jq_server *sv, int timeout_ms, jq_result *out);
+
+int jq_server_release(jq_server *sv, uint64_t ticket);
+int jq_server_stats_get(jq_server *sv, jq_server_stats *out);
+int jq_server_destroy(jq_server *sv);
+
+/* ---- errors ----------------------------------------------------------- */
+
+/* Description of the last error on this thread ("" if none). */
+const char *jq_last_error(void);
+
+/* Library version string. */
+const char *jq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JQ_H */

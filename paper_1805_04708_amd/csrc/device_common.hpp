@@ -1,0 +1,237 @@
+// Device helpers shared by the state-vector and two-byte-code kernels:
+// complex arithmetic, index expansion, and the FP64 reduction kernels, which
+// take a loader so that both storage formats reuse them.
+#pragma once
+
+#include "internal.hpp"
+
+namespace jq {
+
+constexpr int kBlock = 256;
+constexpr int kIt = 4;
+
+template <typename R>
+struct Vec;
+template <>
+struct Vec<double> {
+    using T = double2;
+};
+template <>
+struct Vec<float> {
+    using T = float2;
+};
+
+template <typename R>
+struct Cx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> cadd(Cx<R> a, Cx<R> b) {
+    return {a.re + b.re, a.im + b.im};
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> csel(bool c, Cx<R> a, Cx<R> b) {
+    return {c ? a.re : b.re, c ? a.im : b.im};
+}
+
+template <typename R>
+__device__ __forceinline__ Cx<R> ld(const typename Vec<R>::T* p, uint64_t i) {
+    typename Vec<R>::T v = p[i];
+    return {v.x, v.y};
+}
+template <typename R>
+__device__ __forceinline__ void st(typename Vec<R>::T* p, uint64_t i, Cx<R> a) {
+    typename Vec<R>::T v;
+    v.x = a.re;
+    v.y = a.im;
+    p[i] = v;
+}
+
+// Insert zero bits at sorted positions, then set the bits of `ones`.
+struct Ins {
+    int32_t cnt;
+    int32_t pos[7];
+    uint64_t ones;
+};
+
+__device__ __forceinline__ uint64_t expand(uint64_t g, const Ins& s) {
+    for (int i = 0; i < s.cnt; ++i) {
+        const int p = s.pos[i];
+        g = ((g >> p) << (p + 1)) | (g & ((1ull << p) - 1));
+    }
+    return g | s.ones;
+}
+
+template <typename R>
+struct M4 {
+    Cx<R> e[4];
+};
+template <typename R>
+struct M16 {
+    Cx<R> e[16];
+};
+
+
+
+// Insert zero bits at up to 32 sorted positions (reductions over many qubits).
+struct InsN {
+    int32_t cnt;
+    int32_t pos[32];
+};
+
+__device__ __forceinline__ uint64_t expand_n(uint64_t g, const InsN& s) {
+    for (int i = 0; i < s.cnt; ++i) {
+        const int p = s.pos[i];
+        g = ((g >> p) << (p + 1)) | (g & ((1ull << p) - 1));
+    }
+    return g;
+}
+
+// Fixed-order block sum: within the wave by halving distance, then the
+// waves in order.  Every thread must call it; thread 0 gets the sum.
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += lds[i];
+    __syncthreads();
+    return s;
+}
+
+struct Dep {
+    int32_t nq;
+    int32_t q[30];
+};
+
+// Marginal distribution: block (bin, part) sums |a|^2 over the indices whose
+// selected bits spell `bin`, for its contiguous share of the other bits.
+template <class L>
+__global__ __launch_bounds__(kBlock) void k_probs(L ldr, InsN others, Dep sel, uint64_t n_others, uint32_t parts,
+                                                   double* __restrict__ partial) {
+    __shared__ double lds[kBlock / 64];
+    ldr.prepare();
+    const uint64_t bin = blockIdx.x / parts;
+    const uint64_t part = blockIdx.x % parts;
+    const uint64_t chunk = (n_others + parts - 1) / parts;
+    const uint64_t lo = part * chunk;
+    const uint64_t hi = lo + chunk < n_others ? lo + chunk : n_others;
+    uint64_t binoff = 0;
+    for (int m = 0; m < sel.nq; ++m) binoff |= ((bin >> m) & 1ull) << sel.q[m];
+    double acc = 0.0;
+    for (uint64_t o = lo + threadIdx.x; o < hi; o += kBlock) acc += ldr.modulus2(expand_n(o, others) | binoff);
+    const double s = block_sum(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Few other bits: one thread per bin sums its 2^(N-nq) entries in order.
+template <class L>
+__global__ __launch_bounds__(kBlock) void k_probs_by_bin(L ldr, InsN others, Dep sel, uint64_t n_others,
+                                                          uint64_t nbins, double* __restrict__ out) {
+    ldr.prepare();
+    const uint64_t bin = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (bin >= nbins) return;
+    uint64_t binoff = 0;
+    for (int m = 0; m < sel.nq; ++m) binoff |= ((bin >> m) & 1ull) << sel.q[m];
+    double acc = 0.0;
+    for (uint64_t o = 0; o < n_others; ++o) acc += ldr.modulus2(expand_n(o, others) | binoff);
+    out[bin] = acc;
+}
+
+__global__ void k_sum_parts(const double* __restrict__ partial, uint64_t nbins, uint32_t parts,
+                            double* __restrict__ out);
+
+// Sums over amplitude pairs (i, j = i | 2^q) of 2 Re(conj(a_i) a_j),
+// 2 Im(conj(a_i) a_j), |a_i|^2 - |a_j|^2 and |a_i|^2 + |a_j|^2: the
+// expectations of sigma^x, sigma^y, sigma^z on qubit q and the norm.
+template <class L>
+__global__ __launch_bounds__(kBlock) void k_expect(L ldr, Ins ins, uint64_t qbit, uint64_t npairs, uint32_t parts,
+                                                    double* __restrict__ partial) {
+    __shared__ double lds[kBlock / 64];
+    ldr.prepare();
+    const uint64_t chunk = (npairs + parts - 1) / parts;
+    const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+    const uint64_t hi = lo + chunk < npairs ? lo + chunk : npairs;
+    double sx = 0, sy = 0, sz = 0, nr = 0;
+    for (uint64_t g = lo + threadIdx.x; g < hi; g += kBlock) {
+        const uint64_t i = expand(g, ins);
+        const Cx<double> a = ldr.amp(i), b = ldr.amp(i | qbit);
+        sx += 2.0 * (a.re * b.re + a.im * b.im);
+        sy += 2.0 * (a.re * b.im - a.im * b.re);
+        const double pa = a.re * a.re + a.im * a.im, pb = b.re * b.re + b.im * b.im;
+        sz += pa - pb;
+        nr += pa + pb;
+    }
+    double r[4] = {sx, sy, sz, nr};
+    for (int c = 0; c < 4; ++c) {
+        const double s = block_sum(r[c], lds);
+        if (threadIdx.x == 0) partial[(uint64_t)c * parts + blockIdx.x] = s;
+    }
+}
+
+__global__ void k_expect_final(const double* __restrict__ partial, uint32_t parts, int q, int n,
+                               double* __restrict__ out);
+
+Ins make_ins(uint64_t zero_bits, uint64_t ones);
+unsigned blocks_for(uint64_t items, uint64_t per_block);
+unsigned grid_stride_blocks(uint64_t dim);
+
+template <class L>
+void launch_probs(const L& ldr, int n, const int* qubits, int nq, double* out, double* partial, size_t cap,
+                  hipStream_t st) {
+    uint64_t selmask = 0;
+    Dep d{};
+    d.nq = nq;
+    for (int m = 0; m < nq; ++m) {
+        selmask |= 1ull << qubits[m];
+        d.q[m] = qubits[m];
+    }
+    const uint64_t nbins = 1ull << nq;
+    const uint64_t n_others = 1ull << (n - nq);
+    InsN others{};
+    for (int p = 0; p < n; ++p)
+        if (selmask & (1ull << p)) others.pos[others.cnt++] = p;
+    if (n_others <= 64) {
+        hipLaunchKernelGGL(k_probs_by_bin<L>, dim3(blocks_for(nbins, kBlock)), dim3(kBlock), 0, st, ldr, others, d,
+                           n_others, nbins, out);
+        JQ_HIP(hipGetLastError());
+        return;
+    }
+    uint64_t parts = n_others / (kBlock * 16);
+    if (parts < 1) parts = 1;
+    const uint64_t want = 4096 / nbins + 1;
+    if (parts > want) parts = want;
+    if (nbins * parts > cap) parts = cap / nbins;
+    if (parts < 1) fail(JQ_EINVAL, "reduction scratch too small");
+    hipLaunchKernelGGL(k_probs<L>, dim3((unsigned)(nbins * parts)), dim3(kBlock), 0, st, ldr, others, d, n_others,
+                       (uint32_t)parts, partial);
+    JQ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(nbins, 64)), dim3(64), 0, st, partial, nbins, (uint32_t)parts,
+                       out);
+    JQ_HIP(hipGetLastError());
+}
+
+template <class L>
+void launch_expect(const L& ldr, int n, double* out, double* partial, size_t cap, hipStream_t st) {
+    const uint64_t npairs = 1ull << (n - 1);
+    uint64_t parts = npairs / (kBlock * 16);
+    if (parts < 1) parts = 1;
+    if (parts > 2048) parts = 2048;
+    if (4 * parts > cap) parts = cap / 4;
+    for (int q = 0; q < n; ++q) {
+        const uint64_t qb = 1ull << q;
+        hipLaunchKernelGGL(k_expect<L>, dim3((unsigned)parts), dim3(kBlock), 0, st, ldr, make_ins(qb, 0), qb, npairs,
+                           (uint32_t)parts, partial);
+        hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(64), 0, st, partial, (uint32_t)parts, q, n, out);
+    }
+    JQ_HIP(hipGetLastError());
+}
+
+}  // namespace jq

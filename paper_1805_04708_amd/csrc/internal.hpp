@@ -1,0 +1,216 @@
+// Internal types of the jq library: error plumbing, canonical gate ops, the
+// fused-pass plan, and the launcher entry points of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/jq.h"
+
+namespace jq {
+
+// ---------------------------------------------------------------- errors --
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+[[noreturn]] void fail(int code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+
+#define JQ_HIP(call) ::jq::hip_check((call), #call)
+
+// ------------------------------------------------------- canonical gate --
+
+// A gate reduced to one of four device operations (the planner's input).
+//  DENSE1: 2x2 matrix m[0..3] on target t0.
+//  DENSE2: 4x4 matrix m[0..15] on (t0, t1), t0 the MSB of the matrix index.
+//  DIAG:   multiply by d[sel] where sel is built from the bits of the
+//          nsel selector qubits (t0 the MSB when nsel == 2); nsel == 0
+//          multiplies the whole controlled subset by d[0].
+//  PERMX:  exchange the amplitude pairs that differ in bit t0.
+// Every op acts only where all bits of cmask are 1.
+enum OpKind : int32_t { OP_DENSE1 = 0, OP_DENSE2 = 1, OP_DIAG = 2, OP_PERMX = 3 };
+
+struct cd {
+    double re, im;
+};
+
+struct GateOp {
+    int32_t kind = OP_DENSE1;
+    int32_t t0 = -1, t1 = -1;
+    int32_t nsel = 0;
+    uint64_t cmask = 0;
+    cd m[16] = {};
+    // unimodular diagonal or permutation: leaves every modulus unchanged
+    bool keeps_modulus = false;
+    uint64_t support() const {
+        uint64_t s = cmask;
+        if (t0 >= 0) s |= 1ull << t0;
+        if (t1 >= 0) s |= 1ull << t1;
+        return s;
+    }
+    // number of amplitudes the op reads and writes
+    uint64_t touched(int n) const {
+        int fixed = __builtin_popcountll(cmask);
+        return 1ull << (n - fixed);
+    }
+};
+
+// Lower a jq_gate (ABI form) to a canonical op, validating it against n.
+GateOp canonicalize(const jq_gate& g, int n);
+
+// Lower a named App. A instruction into a jq_gate (throws Error).
+int gate_named(const char* name, const int* qubits, int nq, const double* params, int np, jq_gate* out);
+
+// ------------------------------------------------------- fused passes --
+
+// Lane bits of a wavefront: bits 0..F-1 of the lane id are index bits
+// 0..F-1 (F = 3 for 16-byte amplitudes, so eight lanes cover one 128-byte
+// line); lane bits F..5 map to arbitrary qubits.  A thread holds 2^K
+// amplitudes, register slot bit j being qubit reg_q[j].
+enum FOpKind : int32_t {
+    F_DENSE_REG = 0,
+    F_DENSE_LANE = 1,
+    F_DIAG = 2,
+    F_PERM_REG = 3,
+    F_PERM_LANE = 4,
+};
+
+struct FOp {
+    int32_t kind;
+    int32_t slot;        // register slot bit or lane bit of the target
+    uint32_t reg_ctrl;   // register slots whose bit must be 1
+    int32_t has_ctrl;    // any control at all
+    uint64_t thr_ctrl;   // index bits outside the register slots that must be 1
+    int32_t sel_reg[2];  // diag selector as register slot bit, or -1
+    int32_t sel_glob[2]; // diag selector as index bit (lane/outer), or -1
+    int32_t nsel;
+    int32_t pad;
+    double m[8];         // dense: m00 m01 m10 m11; diag: d0..d3 (complex)
+};
+
+constexpr int kMaxTileBits = 16;
+
+struct FPass {
+    int32_t reg_q[8];
+    int32_t lane_q[6];
+    int32_t n_tile;
+    int32_t tile_sorted[kMaxTileBits];
+    int32_t n_ops;
+    const FOp* ops;      // device pointer
+};
+
+// One step of an execution plan: a single op through a per-gate kernel, or
+// a fused pass over [first_fop, first_fop + n_fops) of the plan's FOp list.
+struct Step {
+    bool fused = false;
+    GateOp op;              // single
+    FPass pass{};           // fused (ops pointer patched after upload)
+    size_t first_fop = 0;
+    int k_reg = 0;          // register bits of the fused kernel
+    size_t n_gates = 0;     // source gates covered
+};
+
+struct PlanConfig {
+    int n = 0;
+    int fixed_lane_bits = 3;  // F
+    int k_reg = 5;            // K
+    int max_ops = 48;
+    bool fuse = true;
+};
+
+struct Plan {
+    std::vector<Step> steps;
+    std::vector<FOp> fops;
+};
+
+Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg);
+
+// ------------------------------------------------------------ kernels --
+
+enum Enc : int32_t { ENC_C128 = JQ_C128, ENC_C64 = JQ_C64, ENC_COMPACT = JQ_COMPACT };
+
+inline int bytes_per_amp(int enc) { return enc == JQ_C128 ? 16 : enc == JQ_C64 ? 8 : 2; }
+
+// state-vector (c128 / c64) launchers; psi is the device buffer
+void sv_init(int enc, void* psi, int n, int mode, uint64_t basis, hipStream_t st);
+void sv_apply_op(int enc, void* psi, int n, const GateOp& op, hipStream_t st);
+void sv_apply_fused(int enc, void* psi, int n, const FPass& pass, int k_reg, int fixed_lane_bits,
+                    hipStream_t st);
+// FP64 marginal distribution; out_dev receives 2^nq doubles (device)
+void sv_probabilities(int enc, const void* psi, int n, const int* qubits, int nq, double* out_dev,
+                      double* partial_dev, size_t partial_cap, hipStream_t st);
+size_t probabilities_partial_count(int n, int nq);
+void sv_expectations(int enc, const void* psi, int n, double* out_dev /* 3*n */, double* partial_dev,
+                     size_t partial_cap, hipStream_t st);
+void sv_scale(int enc, void* psi, int n, double factor, hipStream_t st);
+// convert [first, first+count) to complex128 into dst (device)
+void sv_to_c128(int enc, const void* psi, uint64_t first, uint64_t count, double* dst, hipStream_t st);
+void sv_from_c128(int enc, void* psi, uint64_t first, uint64_t count, const double* src, hipStream_t st);
+
+// two-byte code launchers (planes b0 = codes, b1 = codes + 2^n)
+struct CompactBufs {
+    int8_t* codes;     // b0 plane then b1 plane
+    double* range;     // [2]: current (r0, r1)
+    double* range_next;// [2]: resolved range of the gate in flight
+    uint64_t* acc;     // [2]: min / max of |z| as ordered bit patterns
+};
+void cp_init(const CompactBufs& b, int n, int mode, uint64_t basis, hipStream_t st);
+void cp_apply_op(const CompactBufs& b, int n, const GateOp& op, hipStream_t st);
+void cp_apply_block(const CompactBufs& b, int n, const std::vector<GateOp>& ops, const FPass& pass,
+                    int k_reg, bool keeps_modulus, hipStream_t st);
+void cp_probabilities(const CompactBufs& b, int n, const int* qubits, int nq, double* out_dev,
+                      double* partial_dev, size_t partial_cap, hipStream_t st);
+void cp_expectations(const CompactBufs& b, int n, double* out_dev, double* partial_dev, size_t cap,
+                     hipStream_t st);
+void cp_scale_range(const CompactBufs& b, double factor, hipStream_t st);
+void cp_to_c128(const CompactBufs& b, int n, uint64_t first, uint64_t count, double* dst,
+                hipStream_t st);
+void cp_encode_from_c128(const CompactBufs& b, int n, const double* src, hipStream_t st);
+
+}  // namespace jq
+
+// --------------------------------------------------------------- state --
+
+struct jq_state {
+    int n = 0;
+    int enc = JQ_C128;
+    void* buf = nullptr;         // amplitudes or code planes
+    uint64_t bytes = 0;
+    double* aux = nullptr;       // device scratch: ranges, accumulators, reduction partials
+    size_t aux_doubles = 0;
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*release)(void*, void*) = nullptr;
+    void* alloc_ctx = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    // per-launch timing
+    bool profiling = false;
+    struct Rec {
+        int cls;
+        double bytes;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> event_pool;
+    struct Acc {
+        uint64_t launches = 0;
+        double ms = 0, bytes = 0;
+    };
+    std::vector<Acc> acc;
+    // fused-op list: device copy, pinned staging, event of the last upload
+    void* plan_dev = nullptr;
+    void* plan_host = nullptr;
+    size_t plan_dev_bytes = 0;
+    hipEvent_t plan_ev = nullptr;
+};

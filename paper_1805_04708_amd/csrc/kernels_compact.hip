@@ -1,0 +1,449 @@
+// HIP kernels for the adaptive two-byte polar code of Sec. 4.1.
+//
+// Storage: plane b0 (modulus codes) then plane b1 (phase codes), one int8
+// per amplitude each, plus the FP64 range (r0, r1) in device memory.
+// Decoding: b0 = -128 is 0, b0 = 127 is modulus 1, other codes give
+// r = (b0+127)(r1-r0)/253 + r0; the phase is pi*b1/128.  After a gate the
+// range is recomputed as the min and max of |z| over 0 < |z| < 1 (a
+// modulus >= 1 - 1e-12 counts as one) and every amplitude is re-encoded;
+// a gate that cannot change any modulus (permutation, or diagonal with
+// modulus-one entries) keeps the range.
+//
+// A general gate takes two sweeps with no host round trip: k_cp_gate in
+// range mode decodes, applies the gate in FP64 and reduces min/max |z'|
+// into two ordered 64-bit patterns (atomic min/max: order independent and
+// exact); k_cp_resolve turns them into the new range (or keeps the old one
+// when no modulus lies strictly inside (0, 1)); k_cp_gate in apply mode
+// decodes with the old range, applies, and encodes with the new one.
+// Permutations swap code pairs; modulus-preserving diagonal gates rewrite
+// the phase codes of the touched amplitudes only.
+//
+// This file is compiled with -ffp-contract=off: each product and sum
+// rounds on its own, in the order written, so the codes do not depend on
+// fused multiply-adds.
+#include "device_common.hpp"
+
+namespace jq {
+
+constexpr double kOneTol = 1e-12;
+constexpr double kPiD = 3.14159265358979323846;
+
+// cos/sin(pi*c/128) for c = -128..127, filled from the host C library
+__constant__ double c_cos[256];
+__constant__ double c_sin[256];
+
+struct Range {
+    double r0, r1;
+};
+
+__device__ __forceinline__ Cx<double> decode(int c0, int c1, Range g) {
+    if (c0 == -128) return {0.0, 0.0};
+    const double r = c0 == 127 ? 1.0 : ((double)(c0 + 127) * (g.r1 - g.r0)) / 253.0 + g.r0;
+    return {r * c_cos[c1 + 128], r * c_sin[c1 + 128]};
+}
+
+__device__ __forceinline__ double modulus(Cx<double> z) {
+    return sqrt(z.re * z.re + z.im * z.im);
+}
+
+__device__ __forceinline__ int encode_mod(double a, Range g) {
+    if (a == 0.0) return -128;
+    if (a >= 1.0 - kOneTol) return 127;
+    if (g.r1 == g.r0) return -127;
+    const double q = rint((253.0 * (a - g.r0)) / (g.r1 - g.r0));
+    double v = -127.0 + q;
+    v = v < -127.0 ? -127.0 : v;
+    v = v > 126.0 ? 126.0 : v;
+    return (int)v;
+}
+
+__device__ __forceinline__ int encode_phase(Cx<double> z) {
+    int t = (int)rint((128.0 * atan2(z.im, z.re)) / kPiD);
+    if (t >= 128) t -= 256;
+    if (t < -128) t += 256;
+    return t;
+}
+
+// ordered bit pattern of a non-negative double: integer order = numeric order
+__device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
+
+__device__ __forceinline__ void range_update(double a, double& lo, double& hi) {
+    if (a > 0.0 && a < 1.0 - kOneTol) {
+        lo = a < lo ? a : lo;
+        hi = a > hi ? a : hi;
+    }
+}
+
+__device__ __forceinline__ void range_flush(double lo, double hi, unsigned long long* acc) {
+    // wave-level min/max, then one atomic pair per wave
+    for (int off = 32; off > 0; off >>= 1) {
+        const double l2 = __shfl_xor(lo, off, 64), h2 = __shfl_xor(hi, off, 64);
+        lo = l2 < lo ? l2 : lo;
+        hi = h2 > hi ? h2 : hi;
+    }
+    if ((threadIdx.x & 63) == 0 && hi > 0.0) {
+        atomicMin(&acc[0], dbits(lo));
+        atomicMax(&acc[1], dbits(hi));
+    }
+}
+
+struct CpGate {
+    int32_t kind;     // OP_DENSE1, OP_DENSE2, OP_DIAG
+    int32_t nsel;
+    int32_t t0, t1;
+    uint64_t cmask;
+    Cx<double> m[16];
+};
+
+// Group of the gate: pairs (DENSE1), quads (DENSE2) or single amplitudes
+// (DIAG), over the whole state (controls are tested per group, so that
+// amplitudes outside the controlled subspace are decoded, counted in the
+// range and re-encoded like all others).
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_cp_gate(int8_t* __restrict__ b0, int8_t* __restrict__ b1, uint64_t ngroups,
+                                                     Ins ins, uint64_t hbit, uint64_t lbit, CpGate g,
+                                                     const double* __restrict__ rng_old,
+                                                     const double* __restrict__ rng_new,
+                                                     unsigned long long* __restrict__ acc, int apply) {
+    constexpr int A = KIND == OP_DENSE2 ? 4 : KIND == OP_DENSE1 ? 2 : 1;
+    const Range ro{rng_old[0], rng_old[1]};
+    Range rn = ro;
+    if (apply) rn = Range{rng_new[0], rng_new[1]};
+    double lo = 2.0, hi = 0.0;
+    for (uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x; gi < ngroups;
+         gi += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i = expand(gi, ins);
+        uint64_t idx[A];
+        if constexpr (A == 1) {
+            idx[0] = i;
+        } else if constexpr (A == 2) {
+            idx[0] = i;
+            idx[1] = i | lbit;
+        } else {
+            idx[0] = i;
+            idx[1] = i | lbit;
+            idx[2] = i | hbit;
+            idx[3] = i | hbit | lbit;
+        }
+        Cx<double> z[A], w[A];
+#pragma unroll
+        for (int c = 0; c < A; ++c) z[c] = decode(b0[idx[c]], b1[idx[c]], ro);
+        const bool on = (i & g.cmask) == g.cmask;
+        if constexpr (KIND == OP_DIAG) {
+            int sel = 0;
+            if (g.nsel >= 1) sel = (int)((i >> g.t0) & 1);
+            if (g.nsel == 2) sel = 2 * sel + (int)((i >> g.t1) & 1);
+            w[0] = on ? cmul(g.m[sel], z[0]) : z[0];
+        } else {
+#pragma unroll
+            for (int r = 0; r < A; ++r) {
+                // left-to-right sum of row r, as sum_c m[r][c] z[c]
+                Cx<double> s = cmul(g.m[A * r], z[0]);
+#pragma unroll
+                for (int c = 1; c < A; ++c) s = cadd(s, cmul(g.m[A * r + c], z[c]));
+                w[r] = on ? s : z[r];
+            }
+        }
+        if (!apply) {
+#pragma unroll
+            for (int c = 0; c < A; ++c) range_update(modulus(w[c]), lo, hi);
+        } else {
+#pragma unroll
+            for (int c = 0; c < A; ++c) {
+                const int c0 = encode_mod(modulus(w[c]), rn);
+                b0[idx[c]] = (int8_t)c0;
+                b1[idx[c]] = (int8_t)(c0 == -128 ? 0 : encode_phase(w[c]));
+            }
+        }
+    }
+    if (!apply) range_flush(lo, hi, acc);
+}
+
+__global__ void k_cp_resolve(unsigned long long* acc, const double* rng_old, double* rng_new) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (acc[1] == 0ull) {
+        rng_new[0] = rng_old[0];
+        rng_new[1] = rng_old[1];
+    } else {
+        rng_new[0] = __longlong_as_double((long long)acc[0]);
+        rng_new[1] = __longlong_as_double((long long)acc[1]);
+    }
+    acc[0] = ~0ull;
+    acc[1] = 0ull;
+}
+
+__global__ void k_cp_acc_reset(unsigned long long* acc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        acc[0] = ~0ull;
+        acc[1] = 0ull;
+    }
+}
+
+// Permutation fast path: exchange the code pairs of amplitudes that differ
+// in the target bit, inside the controlled subspace.
+__global__ __launch_bounds__(kBlock) void k_cp_permx(int8_t* __restrict__ b0, int8_t* __restrict__ b1,
+                                                      uint64_t ngroups, Ins ins, uint64_t tbit) {
+    for (uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x; gi < ngroups;
+         gi += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i = expand(gi, ins), j = i | tbit;
+        const int8_t x0 = b0[i], x1 = b1[i], y0 = b0[j], y1 = b1[j];
+        b0[i] = y0;
+        b1[i] = y1;
+        b0[j] = x0;
+        b1[j] = x1;
+    }
+}
+
+// Modulus-preserving diagonal fast path: only the phase codes of the
+// touched amplitudes change (the range is kept, so the modulus code of a
+// decoded-and-rotated amplitude encodes back to itself).
+__global__ __launch_bounds__(kBlock) void k_cp_phase(const int8_t* __restrict__ b0, int8_t* __restrict__ b1,
+                                                      uint64_t ngroups, Ins ins, CpGate g,
+                                                      const double* __restrict__ rng) {
+    const Range r{rng[0], rng[1]};
+    for (uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x; gi < ngroups;
+         gi += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i = expand(gi, ins);
+        const int c0 = b0[i];
+        if (c0 == -128) continue;
+        int sel = 0;
+        if (g.nsel >= 1) sel = (int)((i >> g.t0) & 1);
+        if (g.nsel == 2) sel = 2 * sel + (int)((i >> g.t1) & 1);
+        const Cx<double> w = cmul(g.m[sel], decode(c0, b1[i], r));
+        b1[i] = (int8_t)encode_phase(w);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cp_init(int8_t* __restrict__ b0, int8_t* __restrict__ b1, uint64_t dim,
+                                                     int mode, uint64_t basis, double* rng, double uni) {
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < dim; i += (uint64_t)gridDim.x * kBlock) {
+        if (mode == JQ_INIT_UNIFORM) {
+            b0[i] = -127;
+        } else {
+            b0[i] = i == basis ? (int8_t)127 : (int8_t)-128;
+        }
+        b1[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        rng[0] = mode == JQ_INIT_UNIFORM ? uni : 0.0;
+        rng[1] = mode == JQ_INIT_UNIFORM ? uni : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cp_decode(const int8_t* __restrict__ b0, const int8_t* __restrict__ b1,
+                                                       uint64_t first, uint64_t count, const double* rng,
+                                                       double2* __restrict__ dst) {
+    const Range r{rng[0], rng[1]};
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (uint64_t)gridDim.x * kBlock) {
+        const Cx<double> z = decode(b0[first + i], b1[first + i], r);
+        dst[i] = make_double2(z.re, z.im);
+    }
+}
+
+// Encode a full complex128 state: range pass then encode pass.
+__global__ __launch_bounds__(kBlock) void k_cp_range_of(const double2* __restrict__ src, uint64_t dim,
+                                                         unsigned long long* acc) {
+    double lo = 2.0, hi = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < dim; i += (uint64_t)gridDim.x * kBlock) {
+        const double2 v = src[i];
+        range_update(modulus(Cx<double>{v.x, v.y}), lo, hi);
+    }
+    range_flush(lo, hi, acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cp_encode(const double2* __restrict__ src, uint64_t dim,
+                                                       const double* rng, int8_t* __restrict__ b0,
+                                                       int8_t* __restrict__ b1) {
+    const Range r{rng[0], rng[1]};
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < dim; i += (uint64_t)gridDim.x * kBlock) {
+        const double2 v = src[i];
+        const Cx<double> z{v.x, v.y};
+        const int c0 = encode_mod(modulus(z), r);
+        b0[i] = (int8_t)c0;
+        b1[i] = (int8_t)(c0 == -128 ? 0 : encode_phase(z));
+    }
+}
+
+__global__ void k_cp_scale_range(double* rng, double f) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        rng[0] *= f;
+        rng[1] *= f;
+    }
+}
+
+// Reduction loader: decodes on the fly; the modulus comes from b0 alone.
+struct LoaderCP {
+    const int8_t* b0;
+    const int8_t* b1;
+    const double* rng;
+    Range r;
+    __device__ void prepare() { r = Range{rng[0], rng[1]}; }
+    __device__ __forceinline__ Cx<double> amp(uint64_t i) const { return decode(b0[i], b1[i], r); }
+    __device__ __forceinline__ double modulus2(uint64_t i) const {
+        const int c0 = b0[i];
+        if (c0 == -128) return 0.0;
+        const double m = c0 == 127 ? 1.0 : ((double)(c0 + 127) * (r.r1 - r.r0)) / 253.0 + r.r0;
+        return m * m;
+    }
+};
+
+// ------------------------------------------------------------ launchers --
+
+namespace {
+
+std::once_flag g_lut_once[64];
+
+void ensure_lut() {
+    int dev = 0;
+    JQ_HIP(hipGetDevice(&dev));
+    std::call_once(g_lut_once[dev & 63], [] {
+        double c[256], s[256];
+        for (int k = -128; k < 128; ++k) {
+            const double th = (kPiD * (double)k) / 128.0;
+            c[k + 128] = std::cos(th);
+            s[k + 128] = std::sin(th);
+        }
+        JQ_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_cos), c, sizeof(c)));
+        JQ_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_sin), s, sizeof(s)));
+    });
+}
+
+unsigned persistent_blocks(uint64_t items) {
+    uint64_t b = (items + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    return (unsigned)(b < 16384 ? b : 16384);
+}
+
+CpGate to_cp(const GateOp& op) {
+    CpGate g{};
+    g.kind = op.kind;
+    g.nsel = op.nsel;
+    g.t0 = op.t0 < 0 ? 0 : op.t0;
+    g.t1 = op.t1 < 0 ? 0 : op.t1;
+    g.cmask = op.cmask;
+    for (int i = 0; i < 16; ++i) g.m[i] = Cx<double>{op.m[i].re, op.m[i].im};
+    return g;
+}
+
+}  // namespace
+
+void cp_init(const CompactBufs& b, int n, int mode, uint64_t basis, hipStream_t st) {
+    ensure_lut();
+    const uint64_t dim = 1ull << n;
+    const double uni = 1.0 / std::sqrt(std::ldexp(1.0, n));
+    hipLaunchKernelGGL(k_cp_init, dim3(persistent_blocks(dim)), dim3(kBlock), 0, st, b.codes, b.codes + dim, dim, mode,
+                       basis, b.range, uni);
+    hipLaunchKernelGGL(k_cp_acc_reset, dim3(1), dim3(64), 0, st, (unsigned long long*)b.acc);
+    JQ_HIP(hipGetLastError());
+}
+
+void cp_apply_op(const CompactBufs& b, int n, const GateOp& op, hipStream_t st) {
+    ensure_lut();
+    const uint64_t dim = 1ull << n;
+    int8_t* b0 = b.codes;
+    int8_t* b1 = b.codes + dim;
+    unsigned long long* acc = (unsigned long long*)b.acc;
+    if (op.kind == OP_PERMX) {
+        const uint64_t tb = 1ull << op.t0;
+        const uint64_t ng = 1ull << (n - 1 - __builtin_popcountll(op.cmask));
+        hipLaunchKernelGGL(k_cp_permx, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng,
+                           make_ins(op.cmask | tb, op.cmask), tb);
+        JQ_HIP(hipGetLastError());
+        return;
+    }
+    if (op.kind == OP_DIAG && op.keeps_modulus) {
+        const uint64_t ng = 1ull << (n - __builtin_popcountll(op.cmask));
+        hipLaunchKernelGGL(k_cp_phase, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng,
+                           make_ins(op.cmask, op.cmask), to_cp(op), (const double*)b.range);
+        JQ_HIP(hipGetLastError());
+        return;
+    }
+    const CpGate g = to_cp(op);
+    uint64_t ng = 0, hb = 0, lb = 0;
+    Ins ins{};
+    auto launch = [&](int apply) {
+        const double* rn = b.range_next;
+        switch (op.kind) {
+            case OP_DENSE1:
+                hipLaunchKernelGGL(k_cp_gate<OP_DENSE1>, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng,
+                                   ins, hb, lb, g, (const double*)b.range, rn, acc, apply);
+                break;
+            case OP_DENSE2:
+                hipLaunchKernelGGL(k_cp_gate<OP_DENSE2>, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng,
+                                   ins, hb, lb, g, (const double*)b.range, rn, acc, apply);
+                break;
+            default:
+                hipLaunchKernelGGL(k_cp_gate<OP_DIAG>, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng,
+                                   ins, hb, lb, g, (const double*)b.range, rn, acc, apply);
+                break;
+        }
+        JQ_HIP(hipGetLastError());
+    };
+    if (op.kind == OP_DENSE1) {
+        lb = 1ull << op.t0;
+        ng = dim >> 1;
+        ins = make_ins(lb, 0);
+    } else if (op.kind == OP_DENSE2) {
+        hb = 1ull << op.t0;
+        lb = 1ull << op.t1;
+        ng = dim >> 2;
+        ins = make_ins(hb | lb, 0);
+    } else {
+        ng = dim;
+        ins = make_ins(0, 0);
+    }
+    if (op.keeps_modulus) {
+        // modulus-preserving dense gate (e.g. a permutation matrix given as DENSE): range kept
+        hipLaunchKernelGGL(k_cp_resolve, dim3(1), dim3(64), 0, st, acc, (const double*)b.range, b.range_next);
+        JQ_HIP(hipGetLastError());
+        launch(1);
+    } else {
+        launch(0);
+        hipLaunchKernelGGL(k_cp_resolve, dim3(1), dim3(64), 0, st, acc, (const double*)b.range, b.range_next);
+        JQ_HIP(hipGetLastError());
+        launch(1);
+    }
+    JQ_HIP(hipMemcpyAsync(b.range, b.range_next, 2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+}
+
+void cp_apply_block(const CompactBufs&, int, const std::vector<GateOp>&, const FPass&, int, bool, hipStream_t) {
+    fail(JQ_EUNSUPPORTED, "compact per-block quantisation is not built");
+}
+
+void cp_probabilities(const CompactBufs& b, int n, const int* qubits, int nq, double* out, double* partial, size_t cap,
+                      hipStream_t st) {
+    const uint64_t dim = 1ull << n;
+    launch_probs(LoaderCP{b.codes, b.codes + dim, b.range, {}}, n, qubits, nq, out, partial, cap, st);
+}
+
+void cp_expectations(const CompactBufs& b, int n, double* out, double* partial, size_t cap, hipStream_t st) {
+    ensure_lut();
+    const uint64_t dim = 1ull << n;
+    launch_expect(LoaderCP{b.codes, b.codes + dim, b.range, {}}, n, out, partial, cap, st);
+}
+
+void cp_scale_range(const CompactBufs& b, double f, hipStream_t st) {
+    hipLaunchKernelGGL(k_cp_scale_range, dim3(1), dim3(64), 0, st, b.range, f);
+    JQ_HIP(hipGetLastError());
+}
+
+void cp_to_c128(const CompactBufs& b, int n, uint64_t first, uint64_t count, double* dst, hipStream_t st) {
+    ensure_lut();
+    const uint64_t dim = 1ull << n;
+    hipLaunchKernelGGL(k_cp_decode, dim3(persistent_blocks(count)), dim3(kBlock), 0, st, b.codes, b.codes + dim, first,
+                       count, (const double*)b.range, (double2*)dst);
+    JQ_HIP(hipGetLastError());
+}
+
+void cp_encode_from_c128(const CompactBufs& b, int n, const double* src, hipStream_t st) {
+    const uint64_t dim = 1ull << n;
+    unsigned long long* acc = (unsigned long long*)b.acc;
+    hipLaunchKernelGGL(k_cp_acc_reset, dim3(1), dim3(64), 0, st, acc);
+    hipLaunchKernelGGL(k_cp_range_of, dim3(persistent_blocks(dim)), dim3(kBlock), 0, st, (const double2*)src, dim, acc);
+    hipLaunchKernelGGL(k_cp_resolve, dim3(1), dim3(64), 0, st, acc, (const double*)b.range, b.range);
+    hipLaunchKernelGGL(k_cp_encode, dim3(persistent_blocks(dim)), dim3(kBlock), 0, st, (const double2*)src, dim,
+                       (const double*)b.range, b.codes, b.codes + dim);
+    JQ_HIP(hipGetLastError());
+}
+
+}  // namespace jq

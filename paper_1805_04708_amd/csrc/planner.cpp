@@ -1,0 +1,208 @@
+// Fusion planner: groups consecutive gates into register-blocked tile passes.
+//
+// The paper notes that single- and two-qubit gates stream the whole state
+// for a few flops per amplitude and proposes combining them into
+// multi-qubit blocks to raise the arithmetic intensity (Sec. 5.2).  Here a
+// pass loads a tile of 2^(6+K) amplitudes per wavefront - 64 lanes times
+// 2^K registers - whose index bits are the F low bits (so eight or sixteen
+// lanes read one 128-byte line), 6-F further lane qubits and K register
+// qubits.  Any gate whose target lies in the tile can run in the pass:
+// register targets in-thread, lane targets with cross-lane exchanges.
+// Diagonal gates and controls need no tile bit at all: the index bits they
+// test are known to each thread.
+//
+// Gates may be taken out of order only past gates they commute with: a
+// gate joins the pass only if it shares no qubit with any gate skipped so
+// far (diagonal gates may pass skipped diagonal gates).
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace jq {
+
+namespace {
+
+struct PassBuilder {
+    int n, F, K, max_ops;
+    std::vector<int> reg_q;   // qubits in register slots
+    std::vector<int> lane_q;  // qubits in lane bits F..5
+    std::vector<int> taken;   // op indices
+    uint64_t tile() const {
+        uint64_t t = (1ull << F) - 1;
+        for (int q : reg_q) t |= 1ull << q;
+        for (int q : lane_q) t |= 1ull << q;
+        return t;
+    }
+    // can target q be placed (or is it already)?  Places it if so.
+    bool place(int q) {
+        if (q < F) return true;
+        if (std::find(reg_q.begin(), reg_q.end(), q) != reg_q.end()) return true;
+        if (std::find(lane_q.begin(), lane_q.end(), q) != lane_q.end()) return true;
+        if ((int)reg_q.size() < K) { reg_q.push_back(q); return true; }
+        if ((int)lane_q.size() < 6 - F) { lane_q.push_back(q); return true; }
+        return false;
+    }
+};
+
+double touched_fraction(const GateOp& op, int n) {
+    return std::ldexp((double)op.touched(n), -n);
+}
+
+FOp lower_fop(const GateOp& op, const FPass& p, int F, int K) {
+    FOp f{};
+    auto reg_of = [&](int q) {
+        for (int j = 0; j < K; j++) if (p.reg_q[j] == q) return j;
+        return -1;
+    };
+    auto lane_of = [&](int q) {
+        if (q < F) return q;
+        for (int b = F; b < 6; b++) if (p.lane_q[b] == q) return b;
+        return -1;
+    };
+    uint64_t reg_bits = 0;
+    for (int j = 0; j < K; j++) reg_bits |= 1ull << p.reg_q[j];
+    f.thr_ctrl = op.cmask & ~reg_bits;
+    f.reg_ctrl = 0;
+    for (int j = 0; j < K; j++) if (op.cmask & (1ull << p.reg_q[j])) f.reg_ctrl |= 1u << j;
+    f.has_ctrl = op.cmask != 0;
+    f.sel_reg[0] = f.sel_reg[1] = -1;
+    f.sel_glob[0] = f.sel_glob[1] = -1;
+    if (op.kind == OP_DENSE1 || op.kind == OP_PERMX) {
+        int j = reg_of(op.t0);
+        if (j >= 0) {
+            f.kind = op.kind == OP_DENSE1 ? F_DENSE_REG : F_PERM_REG;
+            f.slot = j;
+        } else {
+            int b = lane_of(op.t0);
+            if (b < 0) fail(JQ_EDEVICE, "planner: target outside the tile");
+            f.kind = op.kind == OP_DENSE1 ? F_DENSE_LANE : F_PERM_LANE;
+            f.slot = b;
+        }
+        for (int i = 0; i < 4; i++) {
+            f.m[2 * i] = op.m[i].re;
+            f.m[2 * i + 1] = op.m[i].im;
+        }
+        return f;
+    }
+    if (op.kind == OP_DIAG) {
+        f.kind = F_DIAG;
+        f.nsel = op.nsel;
+        int sel[2] = {op.t0, op.t1};
+        for (int i = 0; i < op.nsel; i++) {
+            int j = reg_of(sel[i]);
+            if (j >= 0) f.sel_reg[i] = j;
+            else f.sel_glob[i] = sel[i];
+        }
+        for (int i = 0; i < 4; i++) {
+            f.m[2 * i] = op.m[i].re;
+            f.m[2 * i + 1] = op.m[i].im;
+        }
+        return f;
+    }
+    fail(JQ_EDEVICE, "planner: op kind cannot run in a fused pass");
+}
+
+}  // namespace
+
+Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
+    Plan plan;
+    const int n = cfg.n, F = cfg.fixed_lane_bits, K = cfg.k_reg;
+    const bool can_fuse = cfg.fuse && K >= 1 && n >= 6 + K && 6 + K <= kMaxTileBits;
+    if (!can_fuse) {
+        for (const auto& op : ops) {
+            Step s;
+            s.op = op;
+            s.n_gates = 1;
+            plan.steps.push_back(s);
+        }
+        return plan;
+    }
+    std::vector<int> remaining(ops.size());
+    for (size_t i = 0; i < ops.size(); i++) remaining[i] = (int)i;
+    const size_t window = 4096;
+    while (!remaining.empty()) {
+        PassBuilder pb{n, F, K, cfg.max_ops, {}, {}, {}};
+        uint64_t blk_any = 0, blk_diag = 0;
+        size_t scanned = 0;
+        for (size_t r = 0; r < remaining.size() && scanned < window; r++, scanned++) {
+            const GateOp& op = ops[remaining[r]];
+            const uint64_t sup = op.support();
+            const bool diag = op.kind == OP_DIAG;
+            if ((sup & blk_any) || (!diag && (sup & blk_diag))) {
+                (diag ? blk_diag : blk_any) |= sup;
+                continue;
+            }
+            bool ok = true;
+            if (op.kind == OP_DENSE2) {
+                ok = false;  // two-qubit dense blocks run unfused
+            } else if (!diag) {
+                PassBuilder trial = pb;
+                ok = trial.place(op.t0);
+                if (ok) pb = trial;
+            }
+            if (!ok) {
+                (diag ? blk_diag : blk_any) |= sup;
+                continue;
+            }
+            pb.taken.push_back(remaining[r]);
+            if ((int)pb.taken.size() >= cfg.max_ops) break;
+        }
+        if (pb.taken.empty()) {
+            // the first remaining gate cannot run fused: run it alone
+            Step s;
+            s.op = ops[remaining[0]];
+            s.n_gates = 1;
+            plan.steps.push_back(s);
+            remaining.erase(remaining.begin());
+            continue;
+        }
+        // emit singles when they move fewer bytes than one full pass
+        double singles = 0;
+        for (int i : pb.taken) singles += touched_fraction(ops[i], n);
+        std::vector<char> is_taken(ops.size(), 0);
+        for (int i : pb.taken) is_taken[i] = 1;
+        std::vector<int> rest;
+        rest.reserve(remaining.size());
+        for (int i : remaining) if (!is_taken[i]) rest.push_back(i);
+        remaining.swap(rest);
+        if (singles <= 1.0) {
+            for (int i : pb.taken) {
+                Step s;
+                s.op = ops[i];
+                s.n_gates = 1;
+                plan.steps.push_back(s);
+            }
+            continue;
+        }
+        // fill unused slots with the lowest qubits outside the tile
+        uint64_t t = pb.tile();
+        auto next_free = [&]() {
+            for (int q = 0; q < n; q++)
+                if (!(t & (1ull << q))) { t |= 1ull << q; return q; }
+            fail(JQ_EDEVICE, "planner: no free qubit");
+        };
+        while ((int)pb.lane_q.size() < 6 - F) pb.lane_q.push_back(next_free());
+        while ((int)pb.reg_q.size() < K) pb.reg_q.push_back(next_free());
+        Step s;
+        s.fused = true;
+        s.k_reg = K;
+        FPass& p = s.pass;
+        std::memset(&p, 0, sizeof(p));
+        for (int j = 0; j < 8; j++) p.reg_q[j] = j < K ? pb.reg_q[j] : -1;
+        for (int b = 0; b < 6; b++) p.lane_q[b] = b < F ? b : pb.lane_q[b - F];
+        std::vector<int> tb;
+        for (int b = 0; b < 6; b++) tb.push_back(p.lane_q[b]);
+        for (int j = 0; j < K; j++) tb.push_back(p.reg_q[j]);
+        std::sort(tb.begin(), tb.end());
+        p.n_tile = (int)tb.size();
+        for (int i = 0; i < p.n_tile; i++) p.tile_sorted[i] = tb[i];
+        s.first_fop = plan.fops.size();
+        for (int i : pb.taken) plan.fops.push_back(lower_fop(ops[i], p, F, K));
+        p.n_ops = (int)pb.taken.size();
+        s.n_gates = pb.taken.size();
+        plan.steps.push_back(s);
+    }
+    return plan;
+}
+
+}  // namespace jq

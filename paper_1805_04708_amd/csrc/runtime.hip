@@ -1,0 +1,623 @@
+// The C ABI of include/jq.h: state objects, validation, planning and
+// dispatch to the HIP kernels, FP64 reductions, transfers and timing.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace jq {
+
+namespace {
+thread_local std::string g_last_error;
+
+struct AllocHooks {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*release)(void*, void*) = nullptr;
+    void* ctx = nullptr;
+};
+AllocHooks g_hooks;
+std::mutex g_hooks_mu;
+}  // namespace
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void fail(int code, const std::string& msg) { throw Error(code, msg); }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(e == hipErrorOutOfMemory ? JQ_ENOMEM : JQ_EDEVICE,
+                    std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        g_last_error.clear();
+        f();
+        return JQ_OK;
+    } catch (const Error& e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return JQ_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return JQ_EDEVICE;
+    }
+}
+
+// ------------------------------------------------------ kernel timing --
+
+enum KClass { K_DENSE1, K_DENSE2, K_DIAG, K_PERMX, K_FUSED, K_CP_GATE, K_CP_PERM, K_CP_PHASE, K_REDUCE, K_NCLASS };
+const char* kClassName[K_NCLASS] = {"dense1", "dense2", "diag", "permx", "fused",
+                                    "compact_gate", "compact_perm", "compact_phase", "reduce"};
+
+struct Timed {
+    jq_state* s;
+    int cls;
+    double bytes;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(jq_state* st, int c, double by) : s(st), cls(c), bytes(by) {
+        if (!s->profiling) return;
+        a = take();
+        b = take();
+        JQ_HIP(hipEventRecord(a, s->stream));
+    }
+    ~Timed() {
+        if (!s->profiling) return;
+        if (hipEventRecord(b, s->stream) == hipSuccess) s->recs.push_back({cls, bytes, a, b});
+    }
+    hipEvent_t take() {
+        if (s->event_pool.empty()) {
+            hipEvent_t e;
+            JQ_HIP(hipEventCreate(&e));
+            return e;
+        }
+        hipEvent_t e = s->event_pool.back();
+        s->event_pool.pop_back();
+        return e;
+    }
+};
+
+void drain_profile(jq_state* s) {
+    if (s->recs.empty()) return;
+    JQ_HIP(hipStreamSynchronize(s->stream));
+    if (s->acc.size() < K_NCLASS) s->acc.resize(K_NCLASS);
+    for (auto& r : s->recs) {
+        float ms = 0.f;
+        JQ_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        s->acc[r.cls].launches++;
+        s->acc[r.cls].ms += ms;
+        s->acc[r.cls].bytes += r.bytes;
+        s->event_pool.push_back(r.a);
+        s->event_pool.push_back(r.b);
+    }
+    s->recs.clear();
+}
+
+// ---------------------------------------------------------- helpers --
+
+CompactBufs compact_bufs(jq_state* s) {
+    CompactBufs b;
+    b.codes = (int8_t*)s->buf;
+    b.range = s->aux;
+    b.range_next = s->aux + 2;
+    b.acc = (uint64_t*)(s->aux + 4);
+    return b;
+}
+
+constexpr size_t kAuxHead = 8;  // doubles reserved at the start of aux
+
+double* partials(jq_state* s, size_t need) {
+    if (kAuxHead + need > s->aux_doubles) {
+        JQ_HIP(hipStreamSynchronize(s->stream));
+        double* na = nullptr;
+        const size_t cnt = kAuxHead + need;
+        JQ_HIP(hipMalloc(&na, cnt * sizeof(double)));
+        JQ_HIP(hipMemcpy(na, s->aux, kAuxHead * sizeof(double), hipMemcpyDeviceToDevice));
+        JQ_HIP(hipFree(s->aux));
+        s->aux = na;
+        s->aux_doubles = cnt;
+    }
+    return s->aux + kAuxHead;
+}
+
+void check_state(const jq_state* s) {
+    if (!s) fail(JQ_EINVAL, "null state");
+}
+
+double op_bytes(const GateOp& op, int n, int enc) {
+    const double bpa = bytes_per_amp(enc);
+    const double touched = std::ldexp((double)op.touched(n), 0);
+    double amps = touched;
+    if (op.kind == OP_DIAG) amps = touched;  // each touched amplitude read and written once
+    if (enc == JQ_COMPACT) {
+        if (op.kind == OP_PERMX) return 2.0 * amps * 2.0;
+        if (op.kind == OP_DIAG && op.keeps_modulus) return amps * 1.0 + 2.0 * amps * 1.0;
+        const double full = std::ldexp(1.0, n);
+        return op.keeps_modulus ? 2.0 * full * 2.0 : 3.0 * full * 2.0;
+    }
+    return 2.0 * amps * bpa;
+}
+
+int kclass(const GateOp& op, int enc) {
+    if (enc == JQ_COMPACT) {
+        if (op.kind == OP_PERMX) return K_CP_PERM;
+        if (op.kind == OP_DIAG && op.keeps_modulus) return K_CP_PHASE;
+        return K_CP_GATE;
+    }
+    switch (op.kind) {
+        case OP_DENSE1: return K_DENSE1;
+        case OP_DENSE2: return K_DENSE2;
+        case OP_DIAG: return K_DIAG;
+        default: return K_PERMX;
+    }
+}
+
+void run_single(jq_state* s, const GateOp& op) {
+    Timed t(s, kclass(op, s->enc), op_bytes(op, s->n, s->enc));
+    if (s->enc == JQ_COMPACT) cp_apply_op(compact_bufs(s), s->n, op, s->stream);
+    else sv_apply_op(s->enc, s->buf, s->n, op, s->stream);
+}
+
+PlanConfig plan_config(const jq_state* s, const jq_exec_opts* opts) {
+    PlanConfig c;
+    c.n = s->n;
+    c.fixed_lane_bits = s->enc == JQ_C64 ? 4 : 3;
+    c.k_reg = s->enc == JQ_C64 ? 5 : 4;
+    c.max_ops = 48;
+    c.fuse = s->enc != JQ_COMPACT;
+    if (opts) {
+        if (opts->fusion == 1) c.fuse = false;
+        else if (opts->fusion >= 2) c.k_reg = std::min(opts->fusion, s->enc == JQ_C64 ? 6 : 5);
+        if (opts->max_ops > 0) c.max_ops = std::min(opts->max_ops, 256);
+        if (s->enc == JQ_COMPACT && opts->compact_mode == JQ_COMPACT_PER_BLOCK)
+            fail(JQ_EUNSUPPORTED, "compact per-block quantisation is not built");
+    }
+    while (c.fuse && c.k_reg > 2 && c.n < 6 + c.k_reg) c.k_reg--;
+    return c;
+}
+
+// Copy the fused-op list to the device: pinned staging buffer (reused once
+// the previous copy out of it has finished) -> device buffer (reused in
+// stream order, after every kernel that read the previous plan).
+void upload_fops(jq_state* s, const std::vector<FOp>& fops) {
+    const size_t bytes = fops.size() * sizeof(FOp);
+    if (bytes == 0) return;
+    if (s->plan_ev) JQ_HIP(hipEventSynchronize(s->plan_ev));
+    if (bytes > s->plan_dev_bytes) {
+        JQ_HIP(hipStreamSynchronize(s->stream));
+        if (s->plan_dev) JQ_HIP(hipFree(s->plan_dev));
+        if (s->plan_host) JQ_HIP(hipHostFree(s->plan_host));
+        s->plan_dev = nullptr;
+        s->plan_host = nullptr;
+        const size_t cap = std::max<size_t>(bytes * 2, 64 * 1024);
+        JQ_HIP(hipMalloc(&s->plan_dev, cap));
+        JQ_HIP(hipHostMalloc(&s->plan_host, cap, hipHostMallocDefault));
+        s->plan_dev_bytes = cap;
+    }
+    if (!s->plan_ev) JQ_HIP(hipEventCreateWithFlags(&s->plan_ev, hipEventDisableTiming));
+    std::memcpy(s->plan_host, fops.data(), bytes);
+    JQ_HIP(hipMemcpyAsync(s->plan_dev, s->plan_host, bytes, hipMemcpyHostToDevice, s->stream));
+    JQ_HIP(hipEventRecord(s->plan_ev, s->stream));
+}
+
+void apply_ops(jq_state* s, const std::vector<GateOp>& ops, const jq_exec_opts* opts) {
+    const PlanConfig cfg = plan_config(s, opts);
+    Plan plan = make_plan(ops, cfg);
+    upload_fops(s, plan.fops);
+    const FOp* dev = (const FOp*)s->plan_dev;
+    const double full = 2.0 * std::ldexp(1.0, s->n) * bytes_per_amp(s->enc);
+    for (auto& step : plan.steps) {
+        if (!step.fused) {
+            run_single(s, step.op);
+            continue;
+        }
+        FPass p = step.pass;
+        p.ops = dev + step.first_fop;
+        Timed t(s, K_FUSED, full);
+        sv_apply_fused(s->enc, s->buf, s->n, p, step.k_reg, cfg.fixed_lane_bits, s->stream);
+    }
+}
+
+void do_probabilities(jq_state* s, const int* qubits, int nq, double* out_host) {
+    if (nq < 0 || nq > s->n || nq > 30) fail(JQ_EINVAL, "jq_probabilities: bad qubit count");
+    if (nq > 0 && !qubits) fail(JQ_EINVAL, "jq_probabilities: null qubits");
+    if (!out_host) fail(JQ_EINVAL, "jq_probabilities: null output");
+    uint64_t seen = 0;
+    for (int m = 0; m < nq; ++m) {
+        if (qubits[m] < 0 || qubits[m] >= s->n) fail(JQ_EINVAL, "jq_probabilities: qubit out of range");
+        if (seen & (1ull << qubits[m])) fail(JQ_EINVAL, "jq_probabilities: repeated qubit");
+        seen |= 1ull << qubits[m];
+    }
+    const size_t nbins = 1ull << nq;
+    const size_t cap = std::max<size_t>(16384, 2 * nbins);
+    double* scratch = partials(s, nbins + cap);
+    double* out_dev = scratch;
+    double* part = scratch + nbins;
+    {
+        Timed t(s, K_REDUCE, std::ldexp(1.0, s->n) * (s->enc == JQ_COMPACT ? 1 : bytes_per_amp(s->enc)));
+        if (s->enc == JQ_COMPACT) cp_probabilities(compact_bufs(s), s->n, qubits, nq, out_dev, part, cap, s->stream);
+        else sv_probabilities(s->enc, s->buf, s->n, qubits, nq, out_dev, part, cap, s->stream);
+    }
+    JQ_HIP(hipMemcpyAsync(out_host, out_dev, nbins * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    JQ_HIP(hipStreamSynchronize(s->stream));
+}
+
+}  // namespace jq
+
+using namespace jq;
+
+// ================================================================ ABI ==
+
+extern "C" {
+
+const char* jq_last_error(void) { return jq::g_last_error.c_str(); }
+
+const char* jq_version(void) { return "jq 0.1 (gfx950)"; }
+
+int jq_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx) {
+    return guarded([&] {
+        if ((alloc == nullptr) != (release == nullptr)) fail(JQ_EINVAL, "jq_set_allocator: give both or neither");
+        std::lock_guard<std::mutex> lk(g_hooks_mu);
+        g_hooks.alloc = alloc;
+        g_hooks.release = release;
+        g_hooks.ctx = ctx;
+    });
+}
+
+int jq_state_create(int n, jq_encoding enc, jq_state** out) {
+    return guarded([&] {
+        if (!out) fail(JQ_EINVAL, "jq_state_create: null output");
+        *out = nullptr;
+        if (n < 1 || n > JQ_MAX_QUBITS) fail(JQ_EINVAL, "jq_state_create: N must be in [1, 63]");
+        if (enc != JQ_C128 && enc != JQ_C64 && enc != JQ_COMPACT) fail(JQ_EINVAL, "jq_state_create: bad encoding");
+        const int bpa = bytes_per_amp(enc);
+        if (n > 61) fail(JQ_ENOMEM, "jq_state_create: 2^N amplitudes cannot be addressed");
+        const uint64_t bytes = (uint64_t)bpa << n;
+        size_t free_b = 0, total_b = 0;
+        JQ_HIP(hipMemGetInfo(&free_b, &total_b));
+        if (bytes > free_b)
+            fail(JQ_ENOMEM, "jq_state_create: state needs " + std::to_string(bytes) + " bytes, " +
+                                std::to_string(free_b) + " free");
+        auto s = new jq_state();
+        s->n = n;
+        s->enc = enc;
+        s->bytes = bytes;
+        JQ_HIP(hipGetDevice(&s->device));
+        {
+            std::lock_guard<std::mutex> lk(g_hooks_mu);
+            s->alloc = g_hooks.alloc;
+            s->release = g_hooks.release;
+            s->alloc_ctx = g_hooks.ctx;
+        }
+        try {
+            if (s->alloc) {
+                s->buf = s->alloc(bytes, s->alloc_ctx);
+                if (!s->buf) fail(JQ_ENOMEM, "jq_state_create: allocator returned null");
+            } else {
+                JQ_HIP(hipMalloc(&s->buf, bytes));
+            }
+            s->aux_doubles = kAuxHead + 16384 + 64;
+            JQ_HIP(hipMalloc(&s->aux, s->aux_doubles * sizeof(double)));
+            JQ_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+            s->own_stream = true;
+            if (enc == JQ_COMPACT) cp_init(compact_bufs(s), n, JQ_INIT_ZERO, 0, s->stream);
+            else sv_init(enc, s->buf, n, JQ_INIT_ZERO, 0, s->stream);
+        } catch (...) {
+            if (s->buf) {
+                if (s->release) s->release(s->buf, s->alloc_ctx);
+                else (void)hipFree(s->buf);
+            }
+            if (s->aux) (void)hipFree(s->aux);
+            if (s->stream) (void)hipStreamDestroy(s->stream);
+            delete s;
+            throw;
+        }
+        *out = s;
+    });
+}
+
+int jq_state_destroy(jq_state* s) {
+    return guarded([&] {
+        check_state(s);
+        hipError_t e = hipStreamSynchronize(s->stream);
+        for (auto& r : s->recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto ev : s->event_pool) (void)hipEventDestroy(ev);
+        if (s->buf) {
+            if (s->release) s->release(s->buf, s->alloc_ctx);
+            else (void)hipFree(s->buf);
+        }
+        if (s->aux) (void)hipFree(s->aux);
+        if (s->plan_dev) (void)hipFree(s->plan_dev);
+        if (s->plan_host) (void)hipHostFree(s->plan_host);
+        if (s->plan_ev) (void)hipEventDestroy(s->plan_ev);
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        delete s;
+        hip_check(e, "jq_state_destroy: pending work failed");
+    });
+}
+
+int jq_state_init(jq_state* s, jq_init mode, uint64_t basis) {
+    return guarded([&] {
+        check_state(s);
+        if (mode != JQ_INIT_ZERO && mode != JQ_INIT_UNIFORM && mode != JQ_INIT_BASIS)
+            fail(JQ_EINVAL, "jq_state_init: bad mode");
+        if (mode == JQ_INIT_BASIS && basis >= (1ull << s->n)) fail(JQ_EINVAL, "jq_state_init: basis out of range");
+        const uint64_t b = mode == JQ_INIT_BASIS ? basis : 0;
+        if (s->enc == JQ_COMPACT) cp_init(compact_bufs(s), s->n, mode == JQ_INIT_UNIFORM ? 1 : 2, b, s->stream);
+        else sv_init(s->enc, s->buf, s->n, mode == JQ_INIT_UNIFORM ? JQ_INIT_UNIFORM : JQ_INIT_BASIS, b, s->stream);
+    });
+}
+
+int jq_state_info(const jq_state* s, int* n, int* enc, uint64_t* bytes) {
+    return guarded([&] {
+        check_state(s);
+        if (n) *n = s->n;
+        if (enc) *enc = s->enc;
+        if (bytes) *bytes = s->bytes;
+    });
+}
+
+int jq_state_device_ptr(const jq_state* s, void** ptr) {
+    return guarded([&] {
+        check_state(s);
+        if (!ptr) fail(JQ_EINVAL, "null output");
+        *ptr = s->buf;
+    });
+}
+
+int jq_set_stream(jq_state* s, void* stream) {
+    return guarded([&] {
+        check_state(s);
+        hipStream_t ns = (hipStream_t)stream;
+        if (ns == s->stream) return;
+        // order the new stream after the work already queued on the old one
+        hipEvent_t ev;
+        JQ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        JQ_HIP(hipEventRecord(ev, s->stream));
+        if (!ns) {
+            if (!s->own_stream) {
+                JQ_HIP(hipStreamCreateWithFlags(&ns, hipStreamNonBlocking));
+                s->own_stream = true;
+            } else {
+                (void)hipEventDestroy(ev);
+                return;
+            }
+        } else if (s->own_stream) {
+            JQ_HIP(hipStreamWaitEvent(ns, ev, 0));
+            JQ_HIP(hipStreamSynchronize(s->stream));
+            JQ_HIP(hipStreamDestroy(s->stream));
+            s->own_stream = false;
+        }
+        JQ_HIP(hipStreamWaitEvent(ns, ev, 0));
+        JQ_HIP(hipEventDestroy(ev));
+        s->stream = ns;
+    });
+}
+
+int jq_synchronize(jq_state* s) {
+    return guarded([&] {
+        check_state(s);
+        JQ_HIP(hipStreamSynchronize(s->stream));
+    });
+}
+
+int jq_gate_named(const char* name, const int* qubits, int nq, const double* params, int np, jq_gate* out) {
+    return guarded([&] { gate_named(name, qubits, nq, params, np, out); });
+}
+
+int jq_apply_gate(jq_state* s, int kind, const int* qubits, int nq, const int* controls, int nc,
+                  const double* matrix) {
+    return guarded([&] {
+        check_state(s);
+        if (nq < 1 || nq > 2 || !qubits) fail(JQ_EINVAL, "jq_apply_gate: need 1 or 2 qubits");
+        if (nc < 0 || nc > JQ_MAX_CONTROLS || (nc > 0 && !controls)) fail(JQ_EINVAL, "jq_apply_gate: bad controls");
+        jq_gate g;
+        std::memset(&g, 0, sizeof(g));
+        g.kind = kind;
+        g.nq = nq;
+        g.nc = nc;
+        for (int i = 0; i < nq; ++i) g.qubits[i] = qubits[i];
+        for (int i = 0; i < nc; ++i) g.controls[i] = controls[i];
+        if (kind == JQ_DENSE || kind == JQ_DIAGONAL) {
+            if (!matrix) fail(JQ_EINVAL, "jq_apply_gate: null matrix");
+            const int entries = kind == JQ_DENSE ? (1 << nq) * (1 << nq) : (1 << nq);
+            for (int i = 0; i < 2 * entries; ++i) g.m[i] = matrix[i];
+        }
+        run_single(s, canonicalize(g, s->n));
+    });
+}
+
+int jq_apply_circuit(jq_state* s, const jq_gate* gates, size_t count, const jq_exec_opts* opts) {
+    return guarded([&] {
+        check_state(s);
+        if (count && !gates) fail(JQ_EINVAL, "jq_apply_circuit: null gates");
+        std::vector<GateOp> ops;
+        ops.reserve(count);
+        for (size_t i = 0; i < count; ++i) {
+            if (gates[i].nq == 0) continue;  // identity
+            try {
+                ops.push_back(canonicalize(gates[i], s->n));
+            } catch (const Error& e) {
+                fail(e.code, "gate " + std::to_string(i) + ": " + e.what());
+            }
+        }
+        (void)plan_config(s, opts);  // validates options before any work
+        if (s->enc == JQ_COMPACT) {
+            for (const auto& op : ops) run_single(s, op);
+            return;
+        }
+        apply_ops(s, ops, opts);
+    });
+}
+
+int jq_norm(jq_state* s, double* out) {
+    return guarded([&] {
+        check_state(s);
+        if (!out) fail(JQ_EINVAL, "jq_norm: null output");
+        do_probabilities(s, nullptr, 0, out);
+    });
+}
+
+int jq_probabilities(jq_state* s, const int* qubits, int nq, double* out) {
+    return guarded([&] {
+        check_state(s);
+        do_probabilities(s, qubits, nq, out);
+    });
+}
+
+int jq_expectations(jq_state* s, double* qx, double* qy, double* qz) {
+    return guarded([&] {
+        check_state(s);
+        const int n = s->n;
+        const size_t cap = 8192;
+        double* scratch = partials(s, 3 * (size_t)n + cap);
+        {
+            Timed t(s, K_REDUCE, (double)n * std::ldexp(1.0, n) * bytes_per_amp(s->enc));
+            if (s->enc == JQ_COMPACT) cp_expectations(compact_bufs(s), n, scratch, scratch + 3 * n, cap, s->stream);
+            else sv_expectations(s->enc, s->buf, n, scratch, scratch + 3 * n, cap, s->stream);
+        }
+        std::vector<double> h(3 * (size_t)n);
+        JQ_HIP(hipMemcpyAsync(h.data(), scratch, h.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        JQ_HIP(hipStreamSynchronize(s->stream));
+        for (int q = 0; q < n; ++q) {
+            if (qx) qx[q] = h[q];
+            if (qy) qy[q] = h[n + q];
+            if (qz) qz[q] = h[2 * n + q];
+        }
+    });
+}
+
+int jq_renormalize(jq_state* s) {
+    return guarded([&] {
+        check_state(s);
+        double nrm = 0.0;
+        do_probabilities(s, nullptr, 0, &nrm);
+        if (!(nrm > 0.0)) fail(JQ_EZERO, "jq_renormalize: zero norm");
+        const double f = 1.0 / std::sqrt(nrm);
+        if (s->enc == JQ_COMPACT) cp_scale_range(compact_bufs(s), f, s->stream);
+        else sv_scale(s->enc, s->buf, s->n, f, s->stream);
+    });
+}
+
+int jq_read_amplitudes(jq_state* s, uint64_t first, uint64_t count, double* out) {
+    return guarded([&] {
+        check_state(s);
+        const uint64_t dim = 1ull << s->n;
+        if (first > dim || count > dim - first) fail(JQ_EINVAL, "jq_read_amplitudes: range out of bounds");
+        if (count && !out) fail(JQ_EINVAL, "jq_read_amplitudes: null output");
+        if (s->enc == JQ_C128) {
+            JQ_HIP(hipMemcpyAsync(out, (const double*)s->buf + 2 * first, count * 16, hipMemcpyDeviceToHost, s->stream));
+            JQ_HIP(hipStreamSynchronize(s->stream));
+            return;
+        }
+        const uint64_t chunk = 1ull << 22;
+        double* tmp = nullptr;
+        JQ_HIP(hipMalloc(&tmp, std::min(chunk, std::max<uint64_t>(count, 1)) * 16));
+        try {
+            for (uint64_t done = 0; done < count; done += chunk) {
+                const uint64_t c = std::min(chunk, count - done);
+                if (s->enc == JQ_COMPACT) cp_to_c128(compact_bufs(s), s->n, first + done, c, tmp, s->stream);
+                else sv_to_c128(s->enc, s->buf, first + done, c, tmp, s->stream);
+                JQ_HIP(hipMemcpyAsync(out + 2 * done, tmp, c * 16, hipMemcpyDeviceToHost, s->stream));
+                JQ_HIP(hipStreamSynchronize(s->stream));
+            }
+        } catch (...) {
+            (void)hipFree(tmp);
+            throw;
+        }
+        JQ_HIP(hipFree(tmp));
+    });
+}
+
+int jq_write_amplitudes(jq_state* s, uint64_t first, uint64_t count, const double* in) {
+    return guarded([&] {
+        check_state(s);
+        const uint64_t dim = 1ull << s->n;
+        if (first > dim || count > dim - first) fail(JQ_EINVAL, "jq_write_amplitudes: range out of bounds");
+        if (count && !in) fail(JQ_EINVAL, "jq_write_amplitudes: null input");
+        for (uint64_t i = 0; i < 2 * count; ++i)
+            if (!std::isfinite(in[i])) fail(JQ_EINVAL, "jq_write_amplitudes: non-finite value");
+        if (s->enc == JQ_C128) {
+            JQ_HIP(hipMemcpyAsync((double*)s->buf + 2 * first, in, count * 16, hipMemcpyHostToDevice, s->stream));
+            JQ_HIP(hipStreamSynchronize(s->stream));
+            return;
+        }
+        if (s->enc == JQ_COMPACT && (first != 0 || count != dim))
+            fail(JQ_EINVAL, "jq_write_amplitudes: the two-byte code takes only a full write");
+        double* tmp = nullptr;
+        JQ_HIP(hipMalloc(&tmp, std::max<uint64_t>(count, 1) * 16));
+        try {
+            JQ_HIP(hipMemcpyAsync(tmp, in, count * 16, hipMemcpyHostToDevice, s->stream));
+            if (s->enc == JQ_COMPACT) cp_encode_from_c128(compact_bufs(s), s->n, tmp, s->stream);
+            else sv_from_c128(s->enc, s->buf, first, count, tmp, s->stream);
+            JQ_HIP(hipStreamSynchronize(s->stream));
+        } catch (...) {
+            (void)hipFree(tmp);
+            throw;
+        }
+        JQ_HIP(hipFree(tmp));
+    });
+}
+
+int jq_read_codes(jq_state* s, uint64_t first, uint64_t count, int8_t* b0, int8_t* b1, double* range) {
+    return guarded([&] {
+        check_state(s);
+        if (s->enc != JQ_COMPACT) fail(JQ_EINVAL, "jq_read_codes: state is not in the two-byte code");
+        const uint64_t dim = 1ull << s->n;
+        if (first > dim || count > dim - first) fail(JQ_EINVAL, "jq_read_codes: range out of bounds");
+        const int8_t* codes = (const int8_t*)s->buf;
+        if (b0) JQ_HIP(hipMemcpyAsync(b0, codes + first, count, hipMemcpyDeviceToHost, s->stream));
+        if (b1) JQ_HIP(hipMemcpyAsync(b1, codes + dim + first, count, hipMemcpyDeviceToHost, s->stream));
+        if (range) JQ_HIP(hipMemcpyAsync(range, s->aux, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        JQ_HIP(hipStreamSynchronize(s->stream));
+    });
+}
+
+int jq_profile_enable(jq_state* s, int on) {
+    return guarded([&] {
+        check_state(s);
+        if (on) {
+            drain_profile(s);
+            s->acc.assign(K_NCLASS, jq_state::Acc{});
+        } else {
+            drain_profile(s);
+        }
+        s->profiling = on != 0;
+    });
+}
+
+int jq_profile_read(jq_state* s, jq_kernel_stat* out, int max, int* count) {
+    return guarded([&] {
+        check_state(s);
+        drain_profile(s);
+        if (s->acc.size() < K_NCLASS) s->acc.resize(K_NCLASS);
+        int c = 0;
+        for (int k = 0; k < K_NCLASS; ++k) {
+            if (s->acc[k].launches == 0) continue;
+            if (out && c < max) {
+                std::memset(&out[c], 0, sizeof(jq_kernel_stat));
+                std::snprintf(out[c].name, sizeof(out[c].name), "%s", kClassName[k]);
+                out[c].launches = s->acc[k].launches;
+                out[c].total_ms = s->acc[k].ms;
+                out[c].bytes = s->acc[k].bytes;
+            }
+            ++c;
+        }
+        if (count) *count = c;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,321 @@
+"""ctypes binding of ``libjq.so`` (the C ABI in ``include/jq.h``).
+
+Argument marshalling only: every step of gate application, reduction and
+encoding runs in the library's HIP kernels.  The library must be built
+(``python -m paper_1805_04708_amd.build``); importing this module without it
+raises, and there is no fallback.
+
+PyTorch supplies device memory (``use_torch_allocator``) and streams
+(``State.set_stream(torch.cuda.current_stream())``); nothing else of it is
+used.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB
+
+JQ_OK, JQ_EINVAL, JQ_ENOMEM, JQ_EDEVICE, JQ_EUNSUPPORTED, JQ_EZERO, JQ_EBUSY = 0, -1, -2, -3, -4, -5, -6
+JQ_C128, JQ_C64, JQ_COMPACT = 0, 1, 2
+JQ_INIT_ZERO, JQ_INIT_UNIFORM, JQ_INIT_BASIS = 0, 1, 2
+JQ_DENSE, JQ_DIAGONAL, JQ_PERM_X = 0, 1, 2
+JQ_COMPACT_PER_GATE, JQ_COMPACT_PER_BLOCK = 0, 1
+JQ_MAX_CONTROLS = 4
+ENCODINGS = {"c128": JQ_C128, "c64": JQ_C64, "compact": JQ_COMPACT}
+
+
+class JqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nq", ctypes.c_int32), ("nc", ctypes.c_int32),
+                ("qubits", ctypes.c_int32 * 2), ("controls", ctypes.c_int32 * JQ_MAX_CONTROLS),
+                ("pad_", ctypes.c_int32), ("m", ctypes.c_double * 32)]
+
+
+class ExecOpts(ctypes.Structure):
+    _fields_ = [("fusion", ctypes.c_int32), ("compact_mode", ctypes.c_int32), ("max_ops", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+class Circuit(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("pad_", ctypes.c_int32), ("n_gates", ctypes.c_uint64),
+                ("gates", ctypes.POINTER(Gate))]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("n_qubits", ctypes.c_int32),
+                ("norm", ctypes.c_double), ("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double),
+                ("state", ctypes.c_void_p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("throughput_per_s", ctypes.c_double), ("peak_resident_bytes", ctypes.c_uint64)]
+
+
+_VP = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int)
+_BP = ctypes.POINTER(ctypes.c_int8)
+_U64 = ctypes.c_uint64
+
+# name -> (restype, argtypes); every function declared in include/jq.h
+SIGNATURES = {
+    "jq_state_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_VP)]),
+    "jq_state_destroy": (ctypes.c_int, [_VP]),
+    "jq_state_init": (ctypes.c_int, [_VP, ctypes.c_int, _U64]),
+    "jq_state_info": (ctypes.c_int, [_VP, _IP, _IP, ctypes.POINTER(_U64)]),
+    "jq_state_device_ptr": (ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),
+    "jq_set_stream": (ctypes.c_int, [_VP, _VP]),
+    "jq_synchronize": (ctypes.c_int, [_VP]),
+    "jq_set_allocator": (ctypes.c_int, [_VP, _VP, _VP]),
+    "jq_gate_named": (ctypes.c_int, [ctypes.c_char_p, _IP, ctypes.c_int, _DP, ctypes.c_int, ctypes.POINTER(Gate)]),
+    "jq_apply_gate": (ctypes.c_int, [_VP, ctypes.c_int, _IP, ctypes.c_int, _IP, ctypes.c_int, _DP]),
+    "jq_apply_circuit": (ctypes.c_int, [_VP, ctypes.POINTER(Gate), ctypes.c_size_t, ctypes.POINTER(ExecOpts)]),
+    "jq_norm": (ctypes.c_int, [_VP, _DP]),
+    "jq_probabilities": (ctypes.c_int, [_VP, _IP, ctypes.c_int, _DP]),
+    "jq_expectations": (ctypes.c_int, [_VP, _DP, _DP, _DP]),
+    "jq_renormalize": (ctypes.c_int, [_VP]),
+    "jq_read_amplitudes": (ctypes.c_int, [_VP, _U64, _U64, _DP]),
+    "jq_write_amplitudes": (ctypes.c_int, [_VP, _U64, _U64, _DP]),
+    "jq_read_codes": (ctypes.c_int, [_VP, _U64, _U64, _BP, _BP, _DP]),
+    "jq_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "jq_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(KernelStat), ctypes.c_int, _IP]),
+    "jq_batch_create": (ctypes.c_int, [ctypes.POINTER(Circuit), ctypes.c_size_t, ctypes.c_int,
+                                       ctypes.POINTER(ExecOpts), _VP, ctypes.POINTER(_VP)]),
+    "jq_batch_run": (ctypes.c_int, [_VP, _DP]),
+    "jq_batch_read": (ctypes.c_int, [_VP, ctypes.c_size_t, _U64, _U64, _DP]),
+    "jq_batch_destroy": (ctypes.c_int, [_VP]),
+    "jq_server_create": (ctypes.c_int, [_U64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_VP)]),
+    "jq_server_submit": (ctypes.c_int, [_VP, ctypes.POINTER(Circuit), ctypes.c_int, ctypes.POINTER(_U64)]),
+    "jq_server_wait": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(Result)]),
+    "jq_server_release": (ctypes.c_int, [_VP, _U64]),
+    "jq_server_stats_get": (ctypes.c_int, [_VP, ctypes.POINTER(ServerStats)]),
+    "jq_server_destroy": (ctypes.c_int, [_VP]),
+    "jq_last_error": (ctypes.c_char_p, []),
+    "jq_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libjq.so (raises if it has not been built: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise ImportError(f"{LIB} is missing: build it with `python -m paper_1805_04708_amd.build`")
+        L = ctypes.CDLL(LIB)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != JQ_OK:
+        raise JqError(rc, lib().jq_last_error().decode())
+    return rc
+
+
+def _dp(a):
+    return a.ctypes.data_as(_DP)
+
+
+def _ip(a):
+    return a.ctypes.data_as(_IP)
+
+
+# ------------------------------------------------------------- gates --
+
+def gate(name, qubits, params=(), controls=()):
+    """A named instruction (App. A names, plus RZ, CZ, CP, SWAP, MAT1, MAT2)
+    lowered by the library; extra controls are appended."""
+    q = np.ascontiguousarray(list(qubits) or [0], dtype=np.int32)
+    p = np.ascontiguousarray(list(params) or [0.0], dtype=np.float64)
+    g = Gate()
+    check(lib().jq_gate_named(name.encode(), _ip(q), len(qubits), _dp(p), len(params), ctypes.byref(g)))
+    if controls:
+        if g.nc + len(controls) > JQ_MAX_CONTROLS:
+            raise JqError(JQ_EINVAL, "too many controls")
+        for c in controls:
+            g.controls[g.nc] = int(c)
+            g.nc += 1
+    return g
+
+
+def gates(circuit):
+    """Lower a list of (name, qubits, params[, controls]) tuples into a Gate array."""
+    arr = (Gate * max(1, len(circuit)))()
+    for i, g in enumerate(circuit):
+        arr[i] = gate(g[0], g[1], g[2], g[3] if len(g) > 3 else ())
+    return arr, len(circuit)
+
+
+def exec_opts(fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0):
+    o = ExecOpts()
+    o.fusion, o.compact_mode, o.max_ops = fusion, compact_mode, max_ops
+    return o
+
+
+# -------------------------------------------------------------- state --
+
+class State:
+    """An N-qubit state on the current HIP device (owns its device memory)."""
+
+    def __init__(self, n, encoding="c128"):
+        self.n = int(n)
+        self.encoding = ENCODINGS[encoding] if isinstance(encoding, str) else int(encoding)
+        h = _VP()
+        check(lib().jq_state_create(self.n, self.encoding, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            h, self.h = self.h, None
+            check(lib().jq_state_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def nbytes(self):
+        b = _U64()
+        check(lib().jq_state_info(self.h, None, None, ctypes.byref(b)))
+        return b.value
+
+    def init(self, mode=JQ_INIT_ZERO, basis=0):
+        check(lib().jq_state_init(self.h, mode, basis))
+        return self
+
+    def set_stream(self, stream):
+        """stream: a torch.cuda.Stream, an int handle, or None (library stream)."""
+        handle = getattr(stream, "cuda_stream", stream)
+        check(lib().jq_set_stream(self.h, _VP(handle or 0) if handle else None))
+        return self
+
+    def synchronize(self):
+        check(lib().jq_synchronize(self.h))
+
+    def apply_gate(self, kind, qubits, controls=(), matrix=None):
+        q = np.ascontiguousarray(qubits, dtype=np.int32)
+        c = np.ascontiguousarray(list(controls) or [0], dtype=np.int32)
+        m = None
+        if matrix is not None:
+            mc = np.ascontiguousarray(matrix, dtype=np.complex128).ravel()
+            m = np.empty(2 * mc.size)
+            m[0::2], m[1::2] = mc.real, mc.imag
+        check(lib().jq_apply_gate(self.h, kind, _ip(q), len(q), _ip(c), len(controls),
+                                  _dp(m) if m is not None else None))
+        return self
+
+    def apply_circuit(self, circuit, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0):
+        """circuit: list of named gates, or (Gate array, count) from gates()."""
+        arr, cnt = circuit if isinstance(circuit, tuple) else gates(circuit)
+        opts = exec_opts(fusion, compact_mode, max_ops)
+        check(lib().jq_apply_circuit(self.h, arr, cnt, ctypes.byref(opts)))
+        return self
+
+    def norm(self):
+        out = ctypes.c_double()
+        check(lib().jq_norm(self.h, ctypes.byref(out)))
+        return out.value
+
+    def probabilities(self, qubits):
+        q = np.ascontiguousarray(list(qubits) or [0], dtype=np.int32)
+        out = np.zeros(1 << len(qubits))
+        check(lib().jq_probabilities(self.h, _ip(q), len(qubits), _dp(out)))
+        return out
+
+    def expectations(self):
+        qx, qy, qz = np.zeros(self.n), np.zeros(self.n), np.zeros(self.n)
+        check(lib().jq_expectations(self.h, _dp(qx), _dp(qy), _dp(qz)))
+        return qx, qy, qz
+
+    def renormalize(self):
+        check(lib().jq_renormalize(self.h))
+        return self
+
+    def amplitudes(self, first=0, count=None):
+        count = (1 << self.n) - first if count is None else count
+        out = np.zeros(count, dtype=np.complex128)
+        check(lib().jq_read_amplitudes(self.h, first, count, _dp(out.view(np.float64))))
+        return out
+
+    def write_amplitudes(self, psi, first=0):
+        a = np.ascontiguousarray(psi, dtype=np.complex128)
+        check(lib().jq_write_amplitudes(self.h, first, a.size, _dp(a.view(np.float64))))
+        return self
+
+    def codes(self, first=0, count=None):
+        count = (1 << self.n) - first if count is None else count
+        b0 = np.zeros(count, dtype=np.int8)
+        b1 = np.zeros(count, dtype=np.int8)
+        rng = np.zeros(2)
+        check(lib().jq_read_codes(self.h, first, count, b0.ctypes.data_as(_BP), b1.ctypes.data_as(_BP), _dp(rng)))
+        return b0, b1, rng
+
+    def profile(self, on=True):
+        check(lib().jq_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        arr = (KernelStat * 16)()
+        cnt = ctypes.c_int()
+        check(lib().jq_profile_read(self.h, arr, 16, ctypes.byref(cnt)))
+        return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].total_ms, "bytes": arr[i].bytes}
+                for i in range(min(cnt.value, 16))}
+
+
+# ------------------------------------------------------- torch memory --
+
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_torch_hooks = None
+
+
+def use_torch_allocator():
+    """Route state allocations through torch's caching allocator."""
+    global _torch_hooks
+    import torch
+
+    live = {}
+
+    def _alloc(size, ctx):
+        t = torch.empty(int(size), dtype=torch.uint8, device="cuda")
+        live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(ptr, ctx):
+        live.pop(ptr, None)
+
+    a, f = _ALLOC_T(_alloc), _FREE_T(_free)
+    _torch_hooks = (a, f, live)
+    check(lib().jq_set_allocator(ctypes.cast(a, _VP), ctypes.cast(f, _VP), None))
+
+
+def use_hip_allocator():
+    global _torch_hooks
+    check(lib().jq_set_allocator(None, None, None))
+    _torch_hooks = None

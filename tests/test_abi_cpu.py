@@ -1,0 +1,125 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* every function declared in include/jq.h is exported by libjq.so and has a
+  ctypes signature in the binding;
+* the host-only entry points (named-gate lowering, error reporting) work;
+* the library's gate lowering (App. A table written in C++) agrees with the
+  oracle's independent table, for every instruction.
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import gates as OG
+from paper_1805_04708_amd import jq
+from paper_1805_04708_amd.build import LIB, ensure_built
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    ensure_built()
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(jq_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_header_declares_the_core_calls():
+    names = declared_functions()
+    for core in ["jq_state_create", "jq_apply_gate", "jq_apply_circuit", "jq_norm", "jq_probabilities"]:
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(LIB)
+    missing = [n for n in sorted(declared_functions()) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    assert declared_functions() <= set(jq.SIGNATURES), declared_functions() - set(jq.SIGNATURES)
+
+
+def test_struct_layouts_match_header():
+    # jq_gate: 3 int32 + 2 + 4 + pad = 40 bytes, then 32 doubles
+    assert ctypes.sizeof(jq.Gate) == 40 + 32 * 8
+    assert jq.Gate.m.offset == 40
+    assert ctypes.sizeof(jq.ExecOpts) == 32
+    assert ctypes.sizeof(jq.Circuit) == 24
+
+
+def test_version_and_error_strings():
+    assert b"gfx950" in jq.lib().jq_version()
+    with pytest.raises(jq.JqError) as e:
+        jq.gate("NOPE", [0])
+    assert e.value.code == jq.JQ_EINVAL
+    assert "unknown" in jq.lib().jq_last_error().decode()
+    with pytest.raises(jq.JqError):
+        jq.gate("CNOT", [0])          # wrong argument count
+    with pytest.raises(jq.JqError):
+        jq.gate("U3", [0], [1.0])     # wrong parameter count
+
+
+def lowered_full_matrix(g):
+    """Expand a library Gate into (targets, controls, full matrix) in the
+    oracle's convention: X -> [[0,1],[1,0]], DIAGONAL -> diag(entries)."""
+    nq, nc = g.nq, g.nc
+    targets = [g.qubits[i] for i in range(nq)]
+    controls = [g.controls[i] for i in range(nc)]
+    K = 1 << nq
+    m = np.array(g.m[:]).reshape(-1, 2)
+    cm = m[:, 0] + 1j * m[:, 1]
+    if g.kind == jq.JQ_PERM_X:
+        full = np.array([[0, 1], [1, 0]], dtype=complex)
+    elif g.kind == jq.JQ_DIAGONAL:
+        full = np.diag(cm[:K])
+    else:
+        full = cm[:K * K].reshape(K, K)
+    return targets, controls, full
+
+
+def expand(n, targets, controls, m):
+    from oracle import dense
+    return dense.full_matrix(n, targets, controls, m)
+
+
+NAMED = [("I", (0,), ()), ("H", (1,), ()), ("X", (0,), ()), ("Y", (2,), ()), ("Z", (1,), ()),
+         ("S", (0,), ()), ("S+", (0,), ()), ("T", (2,), ()), ("T+", (1,), ()),
+         ("U1", (0,), (0.7,)), ("U2", (1,), (0.3, -1.1)), ("U3", (2,), (1.3, 0.2, -0.4)),
+         ("+X", (0,), ()), ("-X", (1,), ()), ("+Y", (2,), ()), ("-Y", (0,), ()),
+         ("R", (1,), (3,)), ("R", (1,), (-4,)), ("RZ", (2,), (2.5,)),
+         ("CNOT", (2, 0), ()), ("CNOT", (0, 2), ()), ("U", (1, 2), (3,)), ("U", (2, 0), (-2,)),
+         ("CZ", (0, 1), ()), ("CP", (2, 1), (1.1,)), ("SWAP", (0, 2), ()),
+         ("TOFFOLI", (2, 0, 1), ()), ("MAT1", (1,), tuple(np.linspace(-1, 1, 8)))]
+
+
+@pytest.mark.parametrize("g", NAMED, ids=[f"{g[0]}{g[1]}" for g in NAMED])
+def test_named_lowering_matches_oracle_table(g):
+    n = 3
+    lg = jq.gate(*g)
+    t_o, c_o, m_o = OG.lower(g)
+    ref = expand(n, list(t_o), list(c_o), m_o)
+    if lg.nq == 0:  # identity
+        got = np.eye(1 << n)
+    else:
+        t, c, m = lowered_full_matrix(lg)
+        got = expand(n, t, c, m)
+    assert np.allclose(got, ref, atol=1e-15), (g, got, ref)
+
+
+def test_gate_struct_is_copied_controls_appended():
+    g = jq.gate("H", [3], controls=[1, 2])
+    assert g.nc == 2 and list(g.controls[:2]) == [1, 2]
+    assert math.isclose(g.m[0], 1 / math.sqrt(2))

@@ -1,0 +1,322 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Tolerances
+* complex128: relative L2 <= 1e-12 (the target stated for the method);
+* complex64: relative L2 <= 2e-6 per 100 gates (FP32 rounding, ~sqrt(G) * 2^-24
+  growth with margin);
+* reductions: absolute 1e-12 (c128) in FP64.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import core as O
+from oracle import gates as OG
+from paper_1805_04708_amd import jq
+from paper_1805_04708_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    jq.lib()
+
+
+TOL = {"c128": 1e-12, "c64": 2e-6}
+
+
+def run_gpu(n, enc, circuit, fusion=0, init=None):
+    with jq.State(n, enc) as s:
+        if init == "uniform":
+            s.init(jq.JQ_INIT_UNIFORM)
+        elif isinstance(init, int):
+            s.init(jq.JQ_INIT_BASIS, init)
+        elif isinstance(init, np.ndarray):
+            s.write_amplitudes(init)
+        if circuit:
+            s.apply_circuit(circuit, fusion=fusion)
+        return s.amplitudes()
+
+
+def run_oracle(n, circuit, init=None):
+    if init == "uniform":
+        psi = O.uniform_state(n)
+    elif isinstance(init, int):
+        psi = O.basis_state(n, init)
+    elif isinstance(init, np.ndarray):
+        psi = init.astype(np.complex128).copy()
+    else:
+        psi = O.zero_state(n)
+    return O.run(psi, n, circuit)
+
+
+def rand_state(rng, n):
+    psi = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    return psi / np.linalg.norm(psi)
+
+
+def tol(enc, gates=1):
+    return TOL[enc] * (1 if enc == "c128" else max(1.0, math.sqrt(gates / 100.0)))
+
+
+# --------------------------------------------------------------- init --
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 5, 12])
+def test_init_modes(enc, n):
+    assert np.array_equal(run_gpu(n, enc, []), O.zero_state(n))
+    u = run_gpu(n, enc, [], init="uniform")
+    assert np.max(np.abs(u - 2.0 ** (-n / 2))) < 1e-7 if enc == "c64" else np.max(np.abs(u - 2.0 ** (-n / 2))) < 1e-16
+    b = run_gpu(n, enc, [], init=(1 << n) - 1)
+    assert np.array_equal(b, O.basis_state(n, (1 << n) - 1))
+
+
+# ---------------------------------------------------- per-gate kernels --
+
+def single_gate_cases(n, rng):
+    """Every target, with controls below, above and between, for each class."""
+    cases = []
+    for t in range(n):
+        u = W.haar_u2(rng)
+        cases.append(("MAT1", (t,), u))
+        cases.append(("RZ", (t,), (float(rng.uniform(0, 6.28)),)))
+        cases.append(("T", (t,), ()))
+        cases.append(("X", (t,), ()))
+        others = [q for q in range(n) if q != t]
+        if others:
+            c = int(rng.choice(others))
+            cases.append(("CNOT", (c, t), ()))
+            cases.append(("CP", (c, t), (float(rng.uniform(0, 6.28)),)))
+            cases.append(("MAT1", (t,), W.haar_u2(rng), (c,)))
+            cases.append(("SWAP", (t, c), ()))
+            m2 = np.linalg.qr(rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)))[0]
+            flat = np.empty(32)
+            flat[0::2], flat[1::2] = m2.real.ravel(), m2.imag.ravel()
+            cases.append(("MAT2", (c, t), tuple(flat)))
+            cases.append(("RZ", (t,), (0.4,), (c,)))
+        if len(others) >= 2:
+            c1, c2 = (int(x) for x in rng.choice(others, 2, replace=False))
+            cases.append(("TOFFOLI", (c1, c2, t), ()))
+            cases.append(("MAT1", (t,), W.haar_u2(rng), (c1, c2)))
+    return cases
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 2, 3, 6, 7, 11, 14])
+def test_every_gate_class_every_target(enc, n):
+    rng = np.random.default_rng(1000 + n)
+    psi0 = rand_state(rng, n)
+    for g in single_gate_cases(n, rng):
+        got = run_gpu(n, enc, [g], fusion=1, init=psi0)
+        ref = run_oracle(n, [g], init=psi0)
+        assert O.rel_l2(got, ref) <= tol(enc), (enc, n, g[:2], O.rel_l2(got, ref))
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+def test_apply_gate_entry_point(enc):
+    n = 9
+    rng = np.random.default_rng(5)
+    psi0 = rand_state(rng, n)
+    u = OG.matrix("MAT1", W.haar_u2(rng))
+    with jq.State(n, enc) as s:
+        s.write_amplitudes(psi0)
+        s.apply_gate(jq.JQ_DENSE, [4], [7], u)
+        s.apply_gate(jq.JQ_DIAGONAL, [2, 6], [], np.array([1, 1j, -1, np.exp(0.3j)]))
+        s.apply_gate(jq.JQ_PERM_X, [0], [3, 5])
+        got = s.amplitudes()
+    ref = O.apply(psi0.copy(), n, [4], [7], u)
+    ref = O.apply(ref, n, [2, 6], [], np.diag([1, 1j, -1, np.exp(0.3j)]))
+    ref = O.apply(ref, n, [0], [3, 5], OG.matrix("X"))
+    assert O.rel_l2(got, ref) <= tol(enc)
+
+
+def test_invalid_gates_leave_state_untouched():
+    n = 5
+    with jq.State(n, "c128") as s:
+        s.init(jq.JQ_INIT_UNIFORM)
+        before = s.amplitudes()
+        for bad in ([("H", (5,), ())], [("CNOT", (1, 1), ())], [("H", (0,), ()), ("X", (9,), ())]):
+            with pytest.raises(jq.JqError) as e:
+                s.apply_circuit(bad)
+            assert e.value.code == jq.JQ_EINVAL
+        with pytest.raises(jq.JqError):
+            s.apply_gate(jq.JQ_DIAGONAL, [0], [], None)
+        nan = np.array([[np.nan, 0], [0, 1]])
+        with pytest.raises(jq.JqError):
+            s.apply_gate(jq.JQ_DENSE, [0], [], nan)
+        assert np.array_equal(s.amplitudes(), before)
+
+
+# --------------------------------------------------------- circuits --
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+@pytest.mark.parametrize("fusion", [1, 0])
+def test_random_circuit_16_qubits(enc, fusion):
+    # the 16-qubit, 200-gate random circuit workload
+    n = 16
+    circ = W.random_circuit(n, 200, seed=7)
+    got = run_gpu(n, enc, circ, fusion=fusion)
+    ref = run_oracle(n, circ)
+    assert O.rel_l2(got, ref) <= tol(enc, 200), O.rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+@pytest.mark.parametrize("n,fusion", [(10, 0), (13, 0), (17, 0), (17, 3), (18, 2), (19, 5)])
+def test_layered_circuit_fused(enc, n, fusion):
+    if enc == "c128" and fusion > 5:
+        pytest.skip()
+    circ = W.layered_u2_cz(n, 3, seed=n)
+    got = run_gpu(n, enc, circ, fusion=fusion)
+    ref = run_oracle(n, circ)
+    assert O.rel_l2(got, ref) <= tol(enc, len(circ)), O.rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+def test_fused_mixed_gates_with_controls(enc):
+    n = 15
+    rng = np.random.default_rng(9)
+    circ = []
+    for _ in range(300):
+        q = [int(x) for x in rng.permutation(n)]
+        r = rng.random()
+        if r < 0.3:
+            circ.append(("MAT1", (q[0],), W.haar_u2(rng)))
+        elif r < 0.4:
+            circ.append(("MAT1", (q[0],), W.haar_u2(rng), (q[1],)))
+        elif r < 0.55:
+            circ.append(("CNOT", (q[0], q[1]), ()))
+        elif r < 0.65:
+            circ.append(("TOFFOLI", (q[0], q[1], q[2]), ()))
+        elif r < 0.8:
+            circ.append(("CP", (q[0], q[1]), (float(rng.uniform(0, 6)),)))
+        elif r < 0.9:
+            circ.append(("RZ", (q[0],), (float(rng.uniform(0, 6)),)))
+        else:
+            circ.append(("Y", (q[0],), ()))
+    psi0 = rand_state(rng, n)
+    ref = run_oracle(n, circ, init=psi0)
+    for fusion in (0, 2, 3, 4):
+        got = run_gpu(n, enc, circ, fusion=fusion, init=psi0)
+        assert O.rel_l2(got, ref) <= tol(enc, 300), (fusion, O.rel_l2(got, ref))
+
+
+@pytest.mark.parametrize("n", [4, 9, 12])
+def test_closed_forms_on_gpu(n):
+    u = run_gpu(n, "c128", W.hadamard_all(n))
+    assert np.max(np.abs(u - 2.0 ** (-n / 2))) < 1e-15
+    g = run_gpu(n, "c128", W.ghz(n))
+    ref = np.zeros(1 << n, dtype=complex)
+    ref[0] = ref[-1] = 1 / math.sqrt(2)
+    assert np.max(np.abs(g - ref)) < 1e-15
+    x = 5 % (1 << n)
+    q = run_gpu(n, "c128", W.qft(n), init=x)
+    k = np.arange(1 << n)
+    assert np.max(np.abs(q - 2.0 ** (-n / 2) * np.exp(2j * np.pi * x * k / 2 ** n))) < 1e-13
+
+
+# -------------------------------------------------------- reductions --
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 3, 8, 15])
+def test_norm_probabilities_expectations(enc, n):
+    rng = np.random.default_rng(n)
+    circ = W.random_circuit(n, 40, seed=n)
+    ref = run_oracle(n, circ)
+    t = 1e-12 if enc == "c128" else 2e-6
+    with jq.State(n, enc) as s:
+        s.apply_circuit(circ)
+        got = s.amplitudes()
+        assert abs(s.norm() - O.norm2(got, n)) < 1e-12
+        assert abs(s.norm() - 1.0) < t
+        sets = [[], [0], [n - 1], list(range(n))[::-1]]
+        if n >= 3:
+            sets += [[1, 0], [n - 1, 0, 1]]
+        if n >= 8:
+            sets += [[7, 2, 5, 0, 6, 1, 4, 3][: min(n, 8)], [0, 1, 2, 3, 4, 5, 6, 7]]
+        for qs in sets:
+            p = s.probabilities(qs)
+            assert np.max(np.abs(p - O.probabilities(ref, n, qs))) < t, qs
+            # repeated calls give identical bits (fixed summation order)
+            assert np.array_equal(p, s.probabilities(qs))
+        ex = s.expectations()
+        er = O.expect_q(ref, n)
+        for a, b in zip(ex, er):
+            assert np.max(np.abs(a - b)) < t
+        s.apply_gate(jq.JQ_DIAGONAL, [0], [], np.array([2.0, 2.0]))
+        assert abs(s.norm() - 4.0) < 4 * t
+        s.renormalize()
+        assert abs(s.norm() - 1.0) < t
+
+
+def test_probabilities_argument_errors():
+    with jq.State(4, "c128") as s:
+        for bad in ([4], [0, 0], [-1]):
+            with pytest.raises(jq.JqError):
+                s.probabilities(bad)
+
+
+# ------------------------------------------- the two-byte code (Sec. 4.1) --
+
+def compact_compare(n, circ, init=None):
+    """GPU two-byte code vs the oracle's, gate by gate quantisation."""
+    if init == "uniform":
+        st = O.CompactState.encode(O.uniform_state(n), n)
+    else:
+        st = O.CompactState.encode(O.zero_state(n), n)
+    st.run(circ)
+    with jq.State(n, "compact") as s:
+        if init == "uniform":
+            s.init(jq.JQ_INIT_UNIFORM)
+        s.apply_circuit(circ)
+        b0, b1, rng = s.codes()
+        amps = s.amplitudes()
+    return st, b0, b1, rng, amps
+
+
+@pytest.mark.parametrize("n", [3, 8, 12])
+def test_compact_random_circuit_codes(n):
+    circ = W.random_circuit(n, 60, seed=30 + n)
+    st, b0, b1, rng, amps = compact_compare(n, circ)
+    same = np.mean((b0 == st.b0) & (b1 == st.b1))
+    d0 = np.abs(b0.astype(int) - st.b0.astype(int))
+    d1 = np.abs(((b1.astype(int) - st.b1.astype(int)) + 128) % 256 - 128)
+    assert same >= 1 - 1e-4 or (d0.max() <= 1 and d1.max() <= 1), (same, d0.max(), d1.max())
+    assert np.max(np.abs(d0)) <= 1 and np.max(d1) <= 1
+    assert np.allclose(rng, st.rng, rtol=1e-12, atol=0)
+    exact = run_oracle(n, circ)
+    f_gpu, f_or = O.fidelity(amps, exact), O.fidelity(st.decode(), exact)
+    assert 1 - f_gpu <= 2 * (1 - f_or) + 1e-12
+
+
+@pytest.mark.parametrize("n", [5, 11])
+def test_compact_uniform_ghz_exact(n):
+    with jq.State(n, "compact") as s:
+        s.apply_circuit(W.hadamard_all(n))
+        assert np.max(np.abs(s.amplitudes() - 2.0 ** (-n / 2))) < 1e-15
+        s.init(jq.JQ_INIT_ZERO)
+        s.apply_circuit(W.ghz(n))
+        ref = np.zeros(1 << n, dtype=complex)
+        ref[0] = ref[-1] = 1 / math.sqrt(2)
+        assert np.max(np.abs(s.amplitudes() - ref)) < 1e-15
+        assert abs(s.norm() - 1) < 1e-15
+
+
+def test_compact_rz_cnot_chain_matches_oracle_codes():
+    n = 12
+    circ = W.rz_cnot_chain(n, 4, seed=3)
+    st, b0, b1, rng, amps = compact_compare(n, circ, init="uniform")
+    assert np.array_equal(b0, st.b0)
+    d1 = np.abs(((b1.astype(int) - st.b1.astype(int)) + 128) % 256 - 128)
+    assert np.mean(d1 == 0) >= 1 - 1e-4 and d1.max() <= 1
