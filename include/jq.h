@@ -202,6 +202,12 @@ int jq_write_amplitudes(jq_state *s, uint64_t first, uint64_t count, const doubl
  * (may be NULL).  Synchronises. */
 int jq_read_codes(jq_state *s, uint64_t first, uint64_t count, int8_t *b0, int8_t *b1, double *range);
 
+/* Two-byte code only: overwrite all 2^N codes of both planes from host int8
+ * arrays and set the range to range[2] = (r0, r1), 0 <= r0 <= r1 (used
+ * for restoring a saved state).  A zero modulus code (-128) must carry phase
+ * code 0.  Synchronises. */
+int jq_write_codes(jq_state *s, const int8_t *b0, const int8_t *b1, const double *range);
+
 /* ---- per-launch timing ------------------------------------------------ */
 
 typedef struct {

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -138,6 +139,11 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg);
 // ------------------------------------------------------------ kernels --
 
 enum Enc : int32_t { ENC_C128 = JQ_C128, ENC_C64 = JQ_C64, ENC_COMPACT = JQ_COMPACT };
+
+// 2^(-N/2), correctly rounded: exact for even N, sqrt(1/2) * 2^(-(N-1)/2) for odd N
+inline double uniform_amplitude(int n) {
+    return (n % 2 == 0) ? std::ldexp(1.0, -n / 2) : std::ldexp(std::sqrt(0.5), -(n - 1) / 2);
+}
 
 inline int bytes_per_amp(int enc) { return enc == JQ_C128 ? 16 : enc == JQ_C64 ? 8 : 2; }
 

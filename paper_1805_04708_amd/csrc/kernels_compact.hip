@@ -330,7 +330,7 @@ CpGate to_cp(const GateOp& op) {
 void cp_init(const CompactBufs& b, int n, int mode, uint64_t basis, hipStream_t st) {
     ensure_lut();
     const uint64_t dim = 1ull << n;
-    const double uni = 1.0 / std::sqrt(std::ldexp(1.0, n));
+    const double uni = uniform_amplitude(n);
     hipLaunchKernelGGL(k_cp_init, dim3(persistent_blocks(dim)), dim3(kBlock), 0, st, b.codes, b.codes + dim, dim, mode,
                        basis, b.range, uni);
     hipLaunchKernelGGL(k_cp_acc_reset, dim3(1), dim3(64), 0, st, (unsigned long long*)b.acc);

@@ -482,7 +482,7 @@ size_t probabilities_partial_count(int n, int nq) {
 
 void sv_init(int enc, void* psi, int n, int mode, uint64_t basis, hipStream_t st) {
     const uint64_t dim = 1ull << n;
-    const double v = std::ldexp(1.0, 0) / std::sqrt(std::ldexp(1.0, n));
+    const double v = uniform_amplitude(n);
     if (enc == JQ_C128)
         hipLaunchKernelGGL(k_init<double>, dim3(grid_stride_blocks(dim)), dim3(kBlock), 0, st, (double2*)psi, dim,
                            mode, basis, v);

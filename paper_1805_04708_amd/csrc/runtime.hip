@@ -586,6 +586,24 @@ int jq_read_codes(jq_state* s, uint64_t first, uint64_t count, int8_t* b0, int8_
     });
 }
 
+int jq_write_codes(jq_state* s, const int8_t* b0, const int8_t* b1, const double* range) {
+    return guarded([&] {
+        check_state(s);
+        if (s->enc != JQ_COMPACT) fail(JQ_EINVAL, "jq_write_codes: state is not in the two-byte code");
+        if (!b0 || !b1 || !range) fail(JQ_EINVAL, "jq_write_codes: null argument");
+        if (!(range[0] >= 0.0 && range[1] >= range[0] && std::isfinite(range[1])))
+            fail(JQ_EINVAL, "jq_write_codes: need 0 <= r0 <= r1");
+        const uint64_t dim = 1ull << s->n;
+        for (uint64_t i = 0; i < dim; ++i)
+            if (b0[i] == -128 && b1[i] != 0) fail(JQ_EINVAL, "jq_write_codes: zero amplitude with a phase code");
+        int8_t* codes = (int8_t*)s->buf;
+        JQ_HIP(hipMemcpyAsync(codes, b0, dim, hipMemcpyHostToDevice, s->stream));
+        JQ_HIP(hipMemcpyAsync(codes + dim, b1, dim, hipMemcpyHostToDevice, s->stream));
+        JQ_HIP(hipMemcpyAsync(s->aux, range, 2 * sizeof(double), hipMemcpyHostToDevice, s->stream));
+        JQ_HIP(hipStreamSynchronize(s->stream));
+    });
+}
+
 int jq_profile_enable(jq_state* s, int on) {
     return guarded([&] {
         check_state(s);

@@ -90,6 +90,7 @@ SIGNATURES = {
     "jq_read_amplitudes": (ctypes.c_int, [_VP, _U64, _U64, _DP]),
     "jq_write_amplitudes": (ctypes.c_int, [_VP, _U64, _U64, _DP]),
     "jq_read_codes": (ctypes.c_int, [_VP, _U64, _U64, _BP, _BP, _DP]),
+    "jq_write_codes": (ctypes.c_int, [_VP, _BP, _BP, _DP]),
     "jq_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "jq_profile_read": (ctypes.c_int, [_VP, ctypes.POINTER(KernelStat), ctypes.c_int, _IP]),
     "jq_batch_create": (ctypes.c_int, [ctypes.POINTER(Circuit), ctypes.c_size_t, ctypes.c_int,
@@ -276,6 +277,13 @@ class State:
         rng = np.zeros(2)
         check(lib().jq_read_codes(self.h, first, count, b0.ctypes.data_as(_BP), b1.ctypes.data_as(_BP), _dp(rng)))
         return b0, b1, rng
+
+    def write_codes(self, b0, b1, rng):
+        b0 = np.ascontiguousarray(b0, dtype=np.int8)
+        b1 = np.ascontiguousarray(b1, dtype=np.int8)
+        r = np.ascontiguousarray(rng, dtype=np.float64)
+        check(lib().jq_write_codes(self.h, b0.ctypes.data_as(_BP), b1.ctypes.data_as(_BP), _dp(r)))
+        return self
 
     def profile(self, on=True):
         check(lib().jq_profile_enable(self.h, 1 if on else 0))

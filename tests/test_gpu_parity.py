@@ -39,24 +39,24 @@ TOL = {"c128": 1e-12, "c64": 2e-6}
 
 def run_gpu(n, enc, circuit, fusion=0, init=None):
     with jq.State(n, enc) as s:
-        if init == "uniform":
-            s.init(jq.JQ_INIT_UNIFORM)
+        if isinstance(init, np.ndarray):
+            s.write_amplitudes(init)
         elif isinstance(init, int):
             s.init(jq.JQ_INIT_BASIS, init)
-        elif isinstance(init, np.ndarray):
-            s.write_amplitudes(init)
+        elif init == "uniform":
+            s.init(jq.JQ_INIT_UNIFORM)
         if circuit:
             s.apply_circuit(circuit, fusion=fusion)
         return s.amplitudes()
 
 
 def run_oracle(n, circuit, init=None):
-    if init == "uniform":
-        psi = O.uniform_state(n)
+    if isinstance(init, np.ndarray):
+        psi = init.astype(np.complex128).copy()
     elif isinstance(init, int):
         psi = O.basis_state(n, init)
-    elif isinstance(init, np.ndarray):
-        psi = init.astype(np.complex128).copy()
+    elif init == "uniform":
+        psi = O.uniform_state(n)
     else:
         psi = O.zero_state(n)
     return O.run(psi, n, circuit)
@@ -78,7 +78,8 @@ def tol(enc, gates=1):
 def test_init_modes(enc, n):
     assert np.array_equal(run_gpu(n, enc, []), O.zero_state(n))
     u = run_gpu(n, enc, [], init="uniform")
-    assert np.max(np.abs(u - 2.0 ** (-n / 2))) < 1e-7 if enc == "c64" else np.max(np.abs(u - 2.0 ** (-n / 2))) < 1e-16
+    ref = 2.0 ** (-n / 2)
+    assert np.max(np.abs(u - ref)) <= (1e-7 if enc == "c64" else 0.0) * ref
     b = run_gpu(n, enc, [], init=(1 << n) - 1)
     assert np.array_equal(b, O.basis_state(n, (1 << n) - 1))
 
@@ -285,19 +286,80 @@ def compact_compare(n, circ, init=None):
     return st, b0, b1, rng, amps
 
 
+def code_diffs(b0, b1, o0, o1):
+    d0 = np.abs(b0.astype(int) - o0.astype(int))
+    d1 = np.abs(((b1.astype(int) - o1.astype(int)) + 128) % 256 - 128)
+    return d0, d1
+
+
+def random_codes(rng, n, zero_frac=0.1):
+    b0 = rng.integers(-127, 127, 1 << n).astype(np.int8)
+    b1 = rng.integers(-128, 128, 1 << n).astype(np.int8)
+    b0[rng.random(1 << n) < zero_frac] = -128
+    b1[b0 == -128] = 0
+    return b0, b1
+
+
+def one_gate_cases(n, rng):
+    t, c, c2 = (int(x) for x in rng.permutation(n)[:3])
+    return [("MAT1", (t,), W.haar_u2(rng)), ("H", (t,), ()), ("+X", (t,), ()),
+            ("MAT1", (t,), W.haar_u2(rng), (c,)), ("RZ", (t,), (float(rng.uniform(0, 6.28)),)),
+            ("T", (t,), ()), ("CP", (c, t), (float(rng.uniform(0, 6.28)),)), ("CZ", (c, t), ()),
+            ("X", (t,), ()), ("CNOT", (c, t), ()), ("TOFFOLI", (c, c2, t), ()),
+            ("SWAP", (c, t), ()), ("MAT1", (t,), (2.0, 0, 0, 0, 0, 0, 0.5, 0))]
+
+
+@pytest.mark.parametrize("n", [3, 9, 14])
+def test_compact_single_gate_step_matches_oracle(n):
+    # one quantisation step from identical codes: decode, apply, new range,
+    # encode.  Codes may differ only where the value sits on a rounding tie
+    # and the two atan2/sqrt implementations round its last bit differently.
+    rng = np.random.default_rng(70 + n)
+    for g in one_gate_cases(n, rng):
+        b0, b1 = random_codes(rng, n)
+        r0, r1 = 0.01, 0.3
+        st = O.CompactState(n, b0.copy(), b1.copy(), r0, r1).run([g])
+        with jq.State(n, "compact") as s:
+            s.write_codes(b0, b1, (r0, r1))
+            s.apply_circuit([g])
+            g0, g1, rng_gpu = s.codes()
+        d0, d1 = code_diffs(g0, g1, st.b0, st.b1)
+        assert np.array_equal(rng_gpu, st.rng), (g[0], rng_gpu, st.rng)
+        assert d0.max() <= 1 and d1.max() <= 1, (g[0], d0.max(), d1.max())
+        mismatched = int(np.sum((d0 != 0) | (d1 != 0)))
+        assert mismatched <= max(2, 1e-3 * d0.size), (g[0], mismatched)
+
+
 @pytest.mark.parametrize("n", [3, 8, 12])
-def test_compact_random_circuit_codes(n):
+def test_compact_random_circuit(n):
+    # whole circuits: a tie decided differently early on changes later codes,
+    # so the check is on accuracy: the GPU's encoded state is as close to the
+    # exact state as the oracle's (fidelity loss within 2x), and almost all
+    # codes agree.
     circ = W.random_circuit(n, 60, seed=30 + n)
-    st, b0, b1, rng, amps = compact_compare(n, circ)
-    same = np.mean((b0 == st.b0) & (b1 == st.b1))
-    d0 = np.abs(b0.astype(int) - st.b0.astype(int))
-    d1 = np.abs(((b1.astype(int) - st.b1.astype(int)) + 128) % 256 - 128)
-    assert same >= 1 - 1e-4 or (d0.max() <= 1 and d1.max() <= 1), (same, d0.max(), d1.max())
-    assert np.max(np.abs(d0)) <= 1 and np.max(d1) <= 1
-    assert np.allclose(rng, st.rng, rtol=1e-12, atol=0)
+    st = O.CompactState.encode(O.zero_state(n), n).run(circ)
+    with jq.State(n, "compact") as s:
+        s.apply_circuit(circ)
+        b0, b1, rng = s.codes()
+        amps = s.amplitudes()
+    d0, d1 = code_diffs(b0, b1, st.b0, st.b1)
+    assert int(np.sum((d0 != 0) | (d1 != 0))) <= max(2, 0.01 * d0.size)
     exact = run_oracle(n, circ)
     f_gpu, f_or = O.fidelity(amps, exact), O.fidelity(st.decode(), exact)
-    assert 1 - f_gpu <= 2 * (1 - f_or) + 1e-12
+    assert 1 - f_gpu <= 2 * (1 - f_or) + 1e-12, (f_gpu, f_or)
+
+
+@pytest.mark.parametrize("n", [6, 13])
+def test_compact_haar_circuit_codes_identical(n):
+    # no exact ties: Haar U(2) gates and random-angle RZ
+    circ = W.layered_u2_cz(n, 3, seed=n)
+    st = O.CompactState.encode(O.zero_state(n), n).run(circ)
+    with jq.State(n, "compact") as s:
+        s.apply_circuit(circ)
+        b0, b1, rng = s.codes()
+    d0, d1 = code_diffs(b0, b1, st.b0, st.b1)
+    assert np.mean((d0 == 0) & (d1 == 0)) >= 1 - 1e-4
+    assert np.allclose(rng, st.rng, rtol=1e-12, atol=0)
 
 
 @pytest.mark.parametrize("n", [5, 11])
