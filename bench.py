@@ -37,6 +37,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--cpu-gates", type=int, default=3, help="gates of the circuit the CPU oracle times")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="also run a plain torch device copy of this many MiB (counter calibration)")
     return p.parse_args()
 
 
@@ -158,6 +160,20 @@ def main():
 
     state.close()
     torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes,
+                                   "gbps": 2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9}
+        del src, dst
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, circuit, args.cpu_gates)

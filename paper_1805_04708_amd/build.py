@@ -20,8 +20,12 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 # no packed-FP32 instructions anywhere in device code
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-# the two-byte code must round every operation on its own to reproduce codes
-PER_FILE = {"kernels_compact.hip": ["-ffp-contract=off"]}
+# the two-byte code must round every operation on its own to reproduce codes;
+# the fused pass dispatches on wave-uniform op codes, so its branches need no
+# structurisation (which would otherwise merge the whole register tile
+# through chains of copy blocks)
+PER_FILE = {"kernels_compact.hip": ["-ffp-contract=off"],
+            "kernels_sv.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
 
 
 def _sources():

@@ -79,11 +79,17 @@ int gate_named(const char* name, const int* qubits, int nq, const double* params
 // line); lane bits F..5 map to arbitrary qubits.  A thread holds 2^K
 // amplitudes, register slot bit j being qubit reg_q[j].
 enum FOpKind : int32_t {
-    F_DENSE_REG = 0,
-    F_DENSE_LANE = 1,
-    F_DIAG = 2,
-    F_PERM_REG = 3,
-    F_PERM_LANE = 4,
+    F_DENSE_REG = 0,    // 2x2 on a register slot
+    F_CDENSE_REG = 1,   // controlled 2x2 on a register slot
+    F_DENSE_LANE = 2,   // 2x2 on a lane bit
+    F_CDENSE_LANE = 3,  // controlled 2x2 on a lane bit
+    F_PERM_REG = 4,     // X (controlled or not) on a register slot
+    F_PERM_LANE = 5,    // X (controlled or not) on a lane bit
+    F_PHASE = 6,        // multiply the controlled subset by d0
+    F_NEG = 7,          // negate the controlled subset (d0 = -1)
+    F_DIAG = 8,         // diagonal with one or two selector bits
+    F_MDENSE_REG = 9,   // 2x2 on a register slot chosen by 1-2 selector bits
+    F_MDENSE_LANE = 10, // 2x2 on a lane bit chosen by 1-2 selector bits
 };
 
 struct FOp {
@@ -92,11 +98,13 @@ struct FOp {
     uint32_t reg_ctrl;   // register slots whose bit must be 1
     int32_t has_ctrl;    // any control at all
     uint64_t thr_ctrl;   // index bits outside the register slots that must be 1
-    int32_t sel_reg[2];  // diag selector as register slot bit, or -1
-    int32_t sel_glob[2]; // diag selector as index bit (lane/outer), or -1
-    int32_t nsel;
+    int32_t sel_reg[2];  // diag selector / dense multiplexer bit as register slot, or -1
+    int32_t sel_glob[2]; // the same as a thread index bit (lane/outer), or -1
+    int32_t nsel;        // diag: selector bits; dense: multiplexer bits (0..2)
     int32_t pad;
-    double m[8];         // dense: m00 m01 m10 m11; diag: d0..d3 (complex)
+    // dense: matrix v (v = multiplexer value, first selector the MSB) at
+    // m[8v .. 8v+7] as m00 m01 m10 m11; diag: d0..d3
+    double m[32];
 };
 
 constexpr int kMaxTileBits = 16;
@@ -127,6 +135,7 @@ struct PlanConfig {
     int k_reg = 5;            // K
     int max_ops = 48;
     bool fuse = true;
+    bool absorb = true;  // fold diagonal gates into neighbouring dense gates
 };
 
 struct Plan {

@@ -48,7 +48,8 @@ double touched_fraction(const GateOp& op, int n) {
     return std::ldexp((double)op.touched(n), -n);
 }
 
-FOp lower_fop(const GateOp& op, const FPass& p, int F, int K) {
+FOp lower_fop(const GateOp& op, const FPass& p, int F, int K, int nmux = 0, const int* mux = nullptr,
+              const cd (*mats)[4] = nullptr) {
     FOp f{};
     auto reg_of = [&](int q) {
         for (int j = 0; j < K; j++) if (p.reg_q[j] == q) return j;
@@ -68,24 +69,40 @@ FOp lower_fop(const GateOp& op, const FPass& p, int F, int K) {
     f.sel_reg[0] = f.sel_reg[1] = -1;
     f.sel_glob[0] = f.sel_glob[1] = -1;
     if (op.kind == OP_DENSE1 || op.kind == OP_PERMX) {
+        const bool ctrl = op.cmask != 0;
         int j = reg_of(op.t0);
         if (j >= 0) {
-            f.kind = op.kind == OP_DENSE1 ? F_DENSE_REG : F_PERM_REG;
+            f.kind = op.kind == OP_DENSE1 ? (ctrl ? F_CDENSE_REG : F_DENSE_REG) : F_PERM_REG;
             f.slot = j;
         } else {
             int b = lane_of(op.t0);
             if (b < 0) fail(JQ_EDEVICE, "planner: target outside the tile");
-            f.kind = op.kind == OP_DENSE1 ? F_DENSE_LANE : F_PERM_LANE;
+            f.kind = op.kind == OP_DENSE1 ? (ctrl ? F_CDENSE_LANE : F_DENSE_LANE) : F_PERM_LANE;
             f.slot = b;
         }
         for (int i = 0; i < 4; i++) {
             f.m[2 * i] = op.m[i].re;
             f.m[2 * i + 1] = op.m[i].im;
         }
+        if (nmux > 0) {
+            f.kind = (f.kind == F_DENSE_REG) ? F_MDENSE_REG : F_MDENSE_LANE;
+            f.nsel = nmux;
+            for (int i = 0; i < nmux; i++) {
+                int jr = reg_of(mux[i]);
+                if (jr >= 0) f.sel_reg[i] = jr;
+                else f.sel_glob[i] = mux[i];
+            }
+            for (int v = 0; v < (1 << nmux); v++)
+                for (int i = 0; i < 4; i++) {
+                    f.m[8 * v + 2 * i] = mats[v][i].re;
+                    f.m[8 * v + 2 * i + 1] = mats[v][i].im;
+                }
+        }
         return f;
     }
     if (op.kind == OP_DIAG) {
         f.kind = F_DIAG;
+        if (op.nsel == 0) f.kind = (op.m[0].re == -1.0 && op.m[0].im == 0.0) ? F_NEG : F_PHASE;
         f.nsel = op.nsel;
         int sel[2] = {op.t0, op.t1};
         for (int i = 0; i < op.nsel; i++) {
@@ -100,6 +117,98 @@ FOp lower_fop(const GateOp& op, const FPass& p, int F, int K) {
         return f;
     }
     fail(JQ_EDEVICE, "planner: op kind cannot run in a fused pass");
+}
+
+// A gate of a pass with its multiplexer: for each value v of the selector
+// qubits (sel[0] the most significant bit) the 2x2 matrix mats[v].
+struct PassOp {
+    GateOp op;
+    int nsel = 0;
+    int sel[2] = {-1, -1};
+    cd mats[4][4];
+    bool alive = true;
+};
+
+// Value of a diagonal op at a full assignment of its qubits (bit q of idx).
+cd diag_value(const GateOp& d, uint64_t idx) {
+    if ((idx & d.cmask) != d.cmask) return {1.0, 0.0};
+    int sel = 0;
+    if (d.nsel >= 1) sel = (int)((idx >> d.t0) & 1);
+    if (d.nsel == 2) sel = 2 * sel + (int)((idx >> d.t1) & 1);
+    return d.m[sel];
+}
+
+cd cmulh(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+
+// Fold diagonal op d into the uncontrolled dense op u on target t in its
+// support: for every value of the other qubits of d, d acts on t as
+// diag(f0, f1), so u*d (d applied first) has matrix m[r][c] * f_c and d*u
+// has f_r * m[r][c].  The other qubits of d become (further) multiplexer
+// selectors of u.  Returns false if that would need more than two.
+bool absorb(PassOp& u, const GateOp& d, bool d_first, uint64_t reg_bits) {
+    const int t = u.op.t0;
+    uint64_t q = d.support() & ~(1ull << t);
+    int sel[2] = {u.sel[0], u.sel[1]};
+    int nsel = u.nsel;
+    for (int b = 0; b < 64; ++b) {
+        if (!(q & (1ull << b))) continue;
+        if ((nsel >= 1 && sel[0] == b) || (nsel == 2 && sel[1] == b)) continue;
+        if (nsel == 2) return false;
+        sel[nsel++] = b;
+    }
+    // the kernel resolves selectors per thread: none may be a register slot
+    for (int i = 0; i < nsel; ++i)
+        if ((reg_bits >> sel[i]) & 1) return false;
+    cd mats[4][4];
+    for (int v = 0; v < (1 << nsel); ++v) {
+        uint64_t idx = 0;
+        for (int i = 0; i < nsel; ++i)
+            if ((v >> (nsel - 1 - i)) & 1) idx |= 1ull << sel[i];
+        // matrix of u for this selector value
+        int vo = 0;
+        for (int i = 0; i < u.nsel; ++i) vo = 2 * vo + (int)((idx >> u.sel[i]) & 1);
+        const cd* m = u.mats[vo];
+        const cd f0 = diag_value(d, idx), f1 = diag_value(d, idx | (1ull << t));
+        const cd f[2] = {f0, f1};
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) mats[v][2 * r + c] = d_first ? cmulh(m[2 * r + c], f[c]) : cmulh(f[r], m[2 * r + c]);
+    }
+    u.nsel = nsel;
+    u.sel[0] = sel[0];
+    u.sel[1] = sel[1];
+    std::memcpy(u.mats, mats, sizeof(mats));
+    return true;
+}
+
+bool absorbable(const PassOp& p) {
+    return p.alive && p.op.kind == OP_DENSE1 && p.op.cmask == 0;
+}
+
+// Move each diagonal op of the pass onto a neighbouring uncontrolled dense
+// op that acts on one of its qubits, past ops whose (non-diagonal) target
+// lies outside its support; such ops commute with it.
+void absorb_diagonals(std::vector<PassOp>& ops, uint64_t reg_bits) {
+    for (size_t i = 0; i < ops.size(); ++i) {
+        if (!ops[i].alive || ops[i].op.kind != OP_DIAG) continue;
+        const GateOp d = ops[i].op;
+        const uint64_t q = d.support();
+        bool done = false;
+        for (size_t j = i + 1; j < ops.size() && !done; ++j) {
+            PassOp& u = ops[j];
+            if (!u.alive || u.op.kind == OP_DIAG) continue;
+            if (!(q & (1ull << u.op.t0))) continue;
+            if (absorbable(u) && absorb(u, d, true, reg_bits)) done = true;
+            break;
+        }
+        for (size_t j = i; j-- > 0 && !done;) {
+            PassOp& u = ops[j];
+            if (!u.alive || u.op.kind == OP_DIAG) continue;
+            if (!(q & (1ull << u.op.t0))) continue;
+            if (absorbable(u) && absorb(u, d, false, reg_bits)) done = true;
+            break;
+        }
+        if (done) ops[i].alive = false;
+    }
 }
 
 }  // namespace
@@ -197,8 +306,24 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
         p.n_tile = (int)tb.size();
         for (int i = 0; i < p.n_tile; i++) p.tile_sorted[i] = tb[i];
         s.first_fop = plan.fops.size();
-        for (int i : pb.taken) plan.fops.push_back(lower_fop(ops[i], p, F, K));
-        p.n_ops = (int)pb.taken.size();
+        std::vector<PassOp> pops(pb.taken.size());
+        for (size_t i = 0; i < pb.taken.size(); ++i) {
+            pops[i].op = ops[pb.taken[i]];
+            for (int e = 0; e < 4; ++e) pops[i].mats[0][e] = pops[i].op.m[e];
+        }
+        uint64_t reg_bits = 0;
+        for (int j = 0; j < K; ++j) reg_bits |= 1ull << p.reg_q[j];
+        if (cfg.absorb) absorb_diagonals(pops, reg_bits);
+        int n_ops = 0;
+        for (auto& po : pops) {
+            if (!po.alive) continue;
+            // a diagonal on the target alone folds into the matrix itself
+            if (po.op.kind == OP_DENSE1 && po.nsel == 0)
+                for (int e = 0; e < 4; ++e) po.op.m[e] = po.mats[0][e];
+            plan.fops.push_back(lower_fop(po.op, p, F, K, po.nsel, po.sel, po.mats));
+            ++n_ops;
+        }
+        p.n_ops = n_ops;
         s.n_gates = pb.taken.size();
         plan.steps.push_back(s);
     }

@@ -213,6 +213,35 @@ def test_fused_mixed_gates_with_controls(enc):
         assert O.rel_l2(got, ref) <= tol(enc, 300), (fusion, O.rel_l2(got, ref))
 
 
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fused_diagonal_folding(enc, seed):
+    # dense gates surrounded by runs of diagonal gates on their qubits: the
+    # planner folds up to two selector qubits into each dense gate
+    n = 14
+    rng = np.random.default_rng(300 + seed)
+    circ = []
+    for _ in range(120):
+        t = int(rng.integers(n))
+        for _ in range(int(rng.integers(0, 4))):
+            o = int(rng.choice([q for q in range(n) if q != t]))
+            r = rng.random()
+            if r < 0.4:
+                circ.append(("CZ", (o, t), ()))
+            elif r < 0.7:
+                circ.append(("CP", (t, o), (float(rng.uniform(0, 6)),)))
+            elif r < 0.85:
+                circ.append(("RZ", (t,), (float(rng.uniform(0, 6)),)))
+            else:
+                circ.append(("U", (o, t), (int(rng.integers(-5, 6)),)))
+        circ.append(("MAT1", (t,), W.haar_u2(rng)))
+    psi0 = rand_state(rng, n)
+    ref = run_oracle(n, circ, init=psi0)
+    for fusion in (0, 2, 3):
+        got = run_gpu(n, enc, circ, fusion=fusion, init=psi0)
+        assert O.rel_l2(got, ref) <= tol(enc, len(circ)), (fusion, O.rel_l2(got, ref))
+
+
 @pytest.mark.parametrize("n", [4, 9, 12])
 def test_closed_forms_on_gpu(n):
     u = run_gpu(n, "c128", W.hadamard_all(n))
