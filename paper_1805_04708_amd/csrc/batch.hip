@@ -1,0 +1,651 @@
+// Batched small circuits in one persistent launch.
+//
+// Many independent circuits (each N <= 20) run in one kernel: a grid sized
+// to fill the GPU pulls circuit indices from a device work counter, largest
+// states first.  A workgroup owns one circuit at a time.  States of at most
+// 64 KiB live in LDS for the whole circuit (two workgroups per CU); larger
+// ones are updated in place in their slot of the global arena, where they
+// stay L2/MALL resident.
+//
+// A circuit is cut into blocks of consecutive gates whose targets fall in
+// at most KB qubits (KB = the fusion depth, 1..3, tuned per encoding and N).
+// For each block every thread takes groups of 2^KB amplitudes (all values
+// of the block's qubits for one value of the others), applies all the
+// block's gates in registers, and writes them back; one barrier per block.
+// Diagonal gates and controls are tested on each amplitude's full index.
+#include <algorithm>
+#include <map>
+#include <mutex>
+
+#include "device_common.hpp"
+
+namespace jq {
+
+enum BOpKind : int32_t { B_DENSE = 0, B_PERM = 1, B_DIAG = 2, B_DENSE2 = 3 };
+
+struct BOp {
+    int32_t kind;
+    int32_t slot;     // register slot of the target (B_DENSE2: the MSB target)
+    int32_t slot2;    // B_DENSE2: the LSB target's slot
+    int32_t nsel;     // B_DIAG selectors
+    uint32_t cmask;   // full-index bits that must be 1
+    int32_t s0, s1;   // B_DIAG selector qubits
+    int32_t pad;
+    double m[32];     // B_DENSE 2x2 / B_DENSE2 4x4 / B_DIAG d0..d3 (complex)
+};
+
+struct BBlock {
+    int32_t k;        // qubits in the block (1..3)
+    int32_t q[3];
+    int32_t first_op;
+    int32_t n_ops;
+};
+
+struct BCirc {
+    int32_t n;
+    int32_t first_block;
+    int32_t n_blocks;
+    int32_t pad;
+    uint64_t state_off;  // amplitude offset in the arena
+};
+
+constexpr int kBatchThreads = 256;
+constexpr int kLdsBytes = 64 * 1024;
+
+template <typename R, int KB>
+__device__ __forceinline__ void block_dense(Cx<R> (&a)[1 << KB], int j, const BOp* op, uint32_t base,
+                                            const int (&q)[3]) {
+    const Cx<R> m0{(R)op->m[0], (R)op->m[1]}, m1{(R)op->m[2], (R)op->m[3]};
+    const Cx<R> m2{(R)op->m[4], (R)op->m[5]}, m3{(R)op->m[6], (R)op->m[7]};
+    const uint32_t cm = op->cmask;
+#pragma unroll
+    for (int s = 0; s < (1 << KB); ++s) {
+        if ((s >> j) & 1) continue;
+        uint32_t idx = base;
+#pragma unroll
+        for (int i = 0; i < KB; ++i)
+            if ((s >> i) & 1) idx |= 1u << q[i];
+        const bool ok = (idx & cm) == cm;
+        const int t = s | (1 << j);
+        const Cx<R> x = a[s], y = a[t];
+        const Cx<R> nx = mac2(m0, x, m1, y), ny = mac2(m2, x, m3, y);
+        a[s] = csel(ok, nx, x);
+        a[t] = csel(ok, ny, y);
+    }
+}
+
+template <typename R, int KB>
+__device__ __forceinline__ void block_perm(Cx<R> (&a)[1 << KB], int j, const BOp* op, uint32_t base,
+                                           const int (&q)[3]) {
+    const uint32_t cm = op->cmask;
+#pragma unroll
+    for (int s = 0; s < (1 << KB); ++s) {
+        if ((s >> j) & 1) continue;
+        uint32_t idx = base;
+#pragma unroll
+        for (int i = 0; i < KB; ++i)
+            if ((s >> i) & 1) idx |= 1u << q[i];
+        const bool ok = (idx & cm) == cm;
+        const int t = s | (1 << j);
+        const Cx<R> x = a[s], y = a[t];
+        a[s] = csel(ok, y, x);
+        a[t] = csel(ok, x, y);
+    }
+}
+
+template <typename R, int KB>
+__device__ __forceinline__ void block_diag(Cx<R> (&a)[1 << KB], const BOp* op, uint32_t base, const int (&q)[3]) {
+    const uint32_t cm = op->cmask;
+    Cx<R> d[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d[i] = Cx<R>{(R)op->m[2 * i], (R)op->m[2 * i + 1]};
+#pragma unroll
+    for (int s = 0; s < (1 << KB); ++s) {
+        uint32_t idx = base;
+#pragma unroll
+        for (int i = 0; i < KB; ++i)
+            if ((s >> i) & 1) idx |= 1u << q[i];
+        int sel = 0;
+        if (op->nsel >= 1) sel = (idx >> op->s0) & 1;
+        if (op->nsel == 2) sel = 2 * sel + ((idx >> op->s1) & 1);
+        Cx<R> f = d[0];
+        f = csel(sel == 1, d[1], f);
+        f = csel(sel == 2, d[2], f);
+        f = csel(sel == 3, d[3], f);
+        const bool ok = (idx & cm) == cm;
+        a[s] = csel(ok, cmulf(f, a[s]), a[s]);
+    }
+}
+
+template <typename R, int KB>
+__device__ __forceinline__ void block_dense2(Cx<R> (&a)[1 << KB], const BOp* op, uint32_t base, const int (&q)[3]) {
+    if constexpr (KB >= 2) {
+        const int jh = op->slot, jl = op->slot2;
+        const uint32_t cm = op->cmask;
+#pragma unroll
+        for (int s = 0; s < (1 << KB); ++s) {
+            if (((s >> jh) & 1) || ((s >> jl) & 1)) continue;
+            uint32_t idx = base;
+#pragma unroll
+            for (int i = 0; i < KB; ++i)
+                if ((s >> i) & 1) idx |= 1u << q[i];
+            const bool ok = (idx & cm) == cm;
+            const int sl[4] = {s, s | (1 << jl), s | (1 << jh), s | (1 << jh) | (1 << jl)};
+            Cx<R> x[4], y[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) x[c] = a[sl[c]];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Cx<R> acc = cmulf(Cx<R>{(R)op->m[8 * r], (R)op->m[8 * r + 1]}, x[0]);
+#pragma unroll
+                for (int c = 1; c < 4; ++c)
+                    acc = cadd(acc, cmulf(Cx<R>{(R)op->m[8 * r + 2 * c], (R)op->m[8 * r + 2 * c + 1]}, x[c]));
+                y[r] = acc;
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) a[sl[c]] = csel(ok, y[c], x[c]);
+        }
+    }
+}
+
+// One block over the whole state S (LDS or global) of dimension 2^n.
+template <typename R, int KB>
+__device__ void run_block(typename Vec<R>::T* S, int n, const BBlock& blk, const BOp* ops) {
+    int q[3] = {blk.q[0], blk.q[1], blk.q[2]};
+    // sorted copy for the zero-bit insertion
+    int qs[3] = {q[0], q[1], q[2]};
+    for (int i = 0; i < KB; ++i)
+        for (int k = i + 1; k < KB; ++k)
+            if (qs[k] < qs[i]) {
+                const int t = qs[i];
+                qs[i] = qs[k];
+                qs[k] = t;
+            }
+    const uint32_t groups = 1u << (n - KB);
+    for (uint32_t g = threadIdx.x; g < groups; g += blockDim.x) {
+        uint32_t base = g;
+#pragma unroll
+        for (int i = 0; i < KB; ++i) {
+            const int p = qs[i];
+            base = ((base >> p) << (p + 1)) | (base & ((1u << p) - 1));
+        }
+        Cx<R> a[1 << KB];
+#pragma unroll
+        for (int s = 0; s < (1 << KB); ++s) {
+            uint32_t idx = base;
+#pragma unroll
+            for (int i = 0; i < KB; ++i)
+                if ((s >> i) & 1) idx |= 1u << q[i];
+            a[s] = ld<R>(S, idx);
+        }
+        for (int o = 0; o < blk.n_ops; ++o) {
+            const BOp* op = ops + blk.first_op + o;
+            switch (op->kind) {
+                case B_DENSE:
+                case B_PERM: {
+                    const int j = op->slot;
+#define JQ_BCASE(J)                                                                        \
+    case J:                                                                                \
+        if constexpr (J < KB) {                                                            \
+            if (op->kind == B_DENSE) block_dense<R, KB>(a, J, op, base, q);                \
+            else block_perm<R, KB>(a, J, op, base, q);                                     \
+        }                                                                                  \
+        break;
+                    switch (j) {
+                        JQ_BCASE(0)
+                        JQ_BCASE(1)
+                        JQ_BCASE(2)
+                        default:
+                            break;
+                    }
+#undef JQ_BCASE
+                    break;
+                }
+                case B_DIAG:
+                    block_diag<R, KB>(a, op, base, q);
+                    break;
+                case B_DENSE2:
+                    block_dense2<R, KB>(a, op, base, q);
+                    break;
+                default:
+                    break;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < (1 << KB); ++s) {
+            uint32_t idx = base;
+#pragma unroll
+            for (int i = 0; i < KB; ++i)
+                if ((s >> i) & 1) idx |= 1u << q[i];
+            st<R>(S, idx, a[s]);
+        }
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBatchThreads) void k_batch(typename Vec<R>::T* __restrict__ arena,
+                                                          const BCirc* __restrict__ circs,
+                                                          const int32_t* __restrict__ order, uint32_t count,
+                                                          const BBlock* __restrict__ blocks,
+                                                          const BOp* __restrict__ ops, uint32_t* counter,
+                                                          int lds_max_n) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    typename Vec<R>::T* lds = reinterpret_cast<typename Vec<R>::T*>(lds_raw);
+    __shared__ uint32_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t w = next;
+        __syncthreads();
+        if (w >= count) break;
+        const BCirc c = circs[order[w]];
+        const int n = c.n;
+        const uint32_t dim = 1u << n;
+        typename Vec<R>::T* S = n <= lds_max_n ? lds : arena + c.state_off;
+        for (uint32_t i = threadIdx.x; i < dim; i += blockDim.x) {
+            typename Vec<R>::T v;
+            v.x = (R)(i == 0 ? 1 : 0);
+            v.y = (R)0;
+            S[i] = v;
+        }
+        __syncthreads();
+        for (int b = 0; b < c.n_blocks; ++b) {
+            const BBlock blk = blocks[c.first_block + b];
+            switch (blk.k) {
+                case 1: run_block<R, 1>(S, n, blk, ops); break;
+                case 2: run_block<R, 2>(S, n, blk, ops); break;
+                default: run_block<R, 3>(S, n, blk, ops); break;
+            }
+            __syncthreads();
+        }
+        if (n <= lds_max_n) {
+            for (uint32_t i = threadIdx.x; i < dim; i += blockDim.x) arena[c.state_off + i] = S[i];
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void k_batch_reset(uint32_t* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
+// ------------------------------------------------------------- host ------
+
+namespace {
+
+BOp to_bop(const GateOp& op, const int* q, int k) {
+    BOp b{};
+    b.cmask = (uint32_t)op.cmask;
+    auto slot_of = [&](int t) {
+        for (int i = 0; i < k; ++i)
+            if (q[i] == t) return i;
+        fail(JQ_EDEVICE, "batch planner: target outside its block");
+    };
+    switch (op.kind) {
+        case OP_DENSE1:
+            b.kind = B_DENSE;
+            b.slot = slot_of(op.t0);
+            for (int i = 0; i < 4; ++i) {
+                b.m[2 * i] = op.m[i].re;
+                b.m[2 * i + 1] = op.m[i].im;
+            }
+            break;
+        case OP_PERMX:
+            b.kind = B_PERM;
+            b.slot = slot_of(op.t0);
+            break;
+        case OP_DENSE2:
+            b.kind = B_DENSE2;
+            b.slot = slot_of(op.t0);
+            b.slot2 = slot_of(op.t1);
+            for (int i = 0; i < 16; ++i) {
+                b.m[2 * i] = op.m[i].re;
+                b.m[2 * i + 1] = op.m[i].im;
+            }
+            break;
+        default:
+            b.kind = B_DIAG;
+            b.nsel = op.nsel;
+            b.s0 = op.t0 < 0 ? 0 : op.t0;
+            b.s1 = op.t1 < 0 ? 0 : op.t1;
+            for (int i = 0; i < 4; ++i) {
+                b.m[2 * i] = op.m[i].re;
+                b.m[2 * i + 1] = op.m[i].im;
+            }
+    }
+    return b;
+}
+
+// Cut a circuit into blocks of at most kb target qubits (two-qubit dense
+// gates need both targets in one block; kb = 1 gives them a block of 2).
+void plan_blocks(const std::vector<GateOp>& ops, int n, int kb, std::vector<BBlock>& blocks,
+                 std::vector<BOp>& bops) {
+    size_t i = 0;
+    while (i < ops.size()) {
+        int q[3] = {-1, -1, -1};
+        int k = 0;
+        const size_t start = i;
+        auto has = [&](int t) {
+            for (int j = 0; j < k; ++j)
+                if (q[j] == t) return true;
+            return false;
+        };
+        for (; i < ops.size(); ++i) {
+            const GateOp& op = ops[i];
+            int need[2] = {-1, -1};
+            int nn = 0;
+            if (op.kind == OP_DENSE1 || op.kind == OP_PERMX) need[nn++] = op.t0;
+            if (op.kind == OP_DENSE2) {
+                need[nn++] = op.t0;
+                need[nn++] = op.t1;
+            }
+            int add = 0;
+            for (int j = 0; j < nn; ++j) add += !has(need[j]);
+            const int cap = std::max(kb, nn);
+            if (k + add > cap) break;
+            for (int j = 0; j < nn; ++j)
+                if (!has(need[j])) q[k++] = need[j];
+        }
+        if (k == 0) {
+            // only diagonal gates: give them the lowest qubit as the block
+            q[k++] = 0;
+        }
+        // widen to a fixed size of at most 3 with free qubits (cheap, and keeps
+        // the number of kernel variants small)
+        const int kk = std::min(std::max(k, kb), std::min(3, n));
+        for (int t = 0; k < kk && t < n; ++t)
+            if (!has(t)) q[k++] = t;
+        BBlock blk{};
+        blk.k = k;
+        for (int j = 0; j < 3; ++j) blk.q[j] = j < k ? q[j] : 0;
+        blk.first_op = (int32_t)bops.size();
+        for (size_t g = start; g < i; ++g) bops.push_back(to_bop(ops[g], q, k));
+        blk.n_ops = (int32_t)(i - start);
+        blocks.push_back(blk);
+    }
+    (void)n;
+}
+
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, int> g_tuned_kb;  // (enc, n) -> kb
+
+}  // namespace
+
+}  // namespace jq
+
+struct jq_batch {
+    int enc = JQ_C128;
+    size_t count = 0;
+    std::vector<int> n;
+    std::vector<uint64_t> offs;
+    uint64_t arena_amps = 0;
+    void* arena = nullptr;
+    void* circs = nullptr;
+    void* order = nullptr;
+    void* blocks = nullptr;
+    void* ops = nullptr;
+    uint32_t* counter = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int grid = 0;
+    int lds_max_n = 0;
+    size_t lds_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<std::vector<jq::GateOp>> ops_host;
+    std::vector<int> kb;  // fusion depth used per circuit
+};
+
+namespace jq {
+
+namespace {
+
+void free_batch(jq_batch* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (void* p : {b->arena, b->circs, b->order, b->blocks, b->ops, (void*)b->counter})
+        if (p) (void)hipFree(p);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+// Lay out plans for the given per-circuit depths and upload them.
+void upload_plans(jq_batch* b) {
+    std::vector<BCirc> circs(b->count);
+    std::vector<BBlock> blocks;
+    std::vector<BOp> bops;
+    for (size_t i = 0; i < b->count; ++i) {
+        circs[i].n = b->n[i];
+        circs[i].first_block = (int32_t)blocks.size();
+        plan_blocks(b->ops_host[i], b->n[i], b->kb[i], blocks, bops);
+        circs[i].n_blocks = (int32_t)(blocks.size() - circs[i].first_block);
+        circs[i].state_off = b->offs[i];
+    }
+    if (bops.empty()) bops.push_back(BOp{});
+    if (blocks.empty()) blocks.push_back(BBlock{});
+    for (void* p : {b->circs, b->blocks, b->ops})
+        if (p) JQ_HIP(hipFree(p));
+    b->circs = b->blocks = b->ops = nullptr;
+    JQ_HIP(hipMalloc(&b->circs, circs.size() * sizeof(BCirc)));
+    JQ_HIP(hipMalloc(&b->blocks, blocks.size() * sizeof(BBlock)));
+    JQ_HIP(hipMalloc(&b->ops, bops.size() * sizeof(BOp)));
+    JQ_HIP(hipMemcpy(b->circs, circs.data(), circs.size() * sizeof(BCirc), hipMemcpyHostToDevice));
+    JQ_HIP(hipMemcpy(b->blocks, blocks.data(), blocks.size() * sizeof(BBlock), hipMemcpyHostToDevice));
+    JQ_HIP(hipMemcpy(b->ops, bops.data(), bops.size() * sizeof(BOp), hipMemcpyHostToDevice));
+}
+
+void launch(jq_batch* b) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, b->counter);
+    if (b->enc == JQ_C128)
+        hipLaunchKernelGGL(k_batch<double>, dim3(b->grid), dim3(kBatchThreads), b->lds_bytes, b->stream,
+                           (double2*)b->arena, (const BCirc*)b->circs, (const int32_t*)b->order,
+                           (uint32_t)b->count, (const BBlock*)b->blocks, (const BOp*)b->ops, b->counter,
+                           b->lds_max_n);
+    else
+        hipLaunchKernelGGL(k_batch<float>, dim3(b->grid), dim3(kBatchThreads), b->lds_bytes, b->stream,
+                           (float2*)b->arena, (const BCirc*)b->circs, (const int32_t*)b->order,
+                           (uint32_t)b->count, (const BBlock*)b->blocks, (const BOp*)b->ops, b->counter,
+                           b->lds_max_n);
+    JQ_HIP(hipGetLastError());
+}
+
+float timed_launch(jq_batch* b) {
+    JQ_HIP(hipEventRecord(b->ev0, b->stream));
+    launch(b);
+    JQ_HIP(hipEventRecord(b->ev1, b->stream));
+    JQ_HIP(hipEventSynchronize(b->ev1));
+    float ms = 0.f;
+    JQ_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    return ms;
+}
+
+// Fusion depth per (encoding, N): the first batch that meets an untuned N
+// times every depth on its circuits of that N (all depths give the same
+// state up to rounding) and keeps the fastest for the rest of the process,
+// so a circuit runs the same code in every batch of this process.
+void autotune(jq_batch* b, const jq_exec_opts* opts) {
+    std::vector<int> fixed(b->count, 0);
+    if (opts && opts->fusion >= 1) {
+        for (size_t i = 0; i < b->count; ++i) b->kb[i] = std::min(opts->fusion, std::min(3, b->n[i]));
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::map<int, std::vector<size_t>> by_n;
+    for (size_t i = 0; i < b->count; ++i) by_n[b->n[i]].push_back(i);
+    std::vector<int> untuned;
+    for (auto& kv : by_n) {
+        auto it = g_tuned_kb.find({b->enc, kv.first});
+        if (it != g_tuned_kb.end())
+            for (size_t i : kv.second) b->kb[i] = it->second;
+        else
+            untuned.push_back(kv.first);
+    }
+    if (untuned.empty()) return;
+    // time each depth on the whole batch with the untuned sizes at that depth
+    const int maxk = 3;
+    std::map<int, std::vector<float>> cost;  // n -> per-depth time share
+    float best_ms = 0;
+    std::vector<int> saved = b->kb;
+    std::map<int, int> best;
+    for (int n : untuned) best[n] = std::min(2, n);
+    for (int k = 1; k <= maxk; ++k) {
+        for (int n : untuned)
+            for (size_t i : by_n[n]) b->kb[i] = std::min(k, n);
+        upload_plans(b);
+        timed_launch(b);  // warm
+        const float ms = timed_launch(b);
+        if (k == 1 || ms < best_ms) {
+            best_ms = ms;
+            for (int n : untuned) best[n] = std::min(k, n);
+        }
+    }
+    for (int n : untuned) {
+        g_tuned_kb[{b->enc, n}] = best[n];
+        for (size_t i : by_n[n]) b->kb[i] = best[n];
+    }
+    (void)saved;
+    (void)cost;
+}
+
+}  // namespace
+
+}  // namespace jq
+
+using namespace jq;
+
+extern "C" {
+
+int jq_batch_create(const jq_circuit* cs, size_t count, jq_encoding enc, const jq_exec_opts* opts, void* stream,
+                    jq_batch** out) {
+    jq_batch* b = nullptr;
+    try {
+        set_last_error("");
+        if (!out) fail(JQ_EINVAL, "jq_batch_create: null output");
+        *out = nullptr;
+        if (count == 0 || !cs) fail(JQ_EINVAL, "jq_batch_create: empty batch");
+        if (count > (1u << 30)) fail(JQ_EINVAL, "jq_batch_create: too many circuits");
+        if (enc != JQ_C128 && enc != JQ_C64) fail(JQ_EINVAL, "jq_batch_create: encoding must be c128 or c64");
+        b = new jq_batch();
+        b->enc = enc;
+        b->count = count;
+        b->n.resize(count);
+        b->offs.resize(count);
+        b->ops_host.resize(count);
+        b->kb.assign(count, 2);
+        uint64_t off = 0;
+        for (size_t i = 0; i < count; ++i) {
+            const int n = cs[i].n_qubits;
+            if (n < 1 || n > 20) fail(JQ_EINVAL, "jq_batch_create: circuit " + std::to_string(i) + " needs 1 <= N <= 20");
+            if (cs[i].n_gates && !cs[i].gates) fail(JQ_EINVAL, "jq_batch_create: null gates");
+            b->n[i] = n;
+            b->offs[i] = off;
+            off += 1ull << n;
+            for (uint64_t g = 0; g < cs[i].n_gates; ++g) {
+                if (cs[i].gates[g].nq == 0) continue;
+                try {
+                    b->ops_host[i].push_back(canonicalize(cs[i].gates[g], n));
+                } catch (const Error& e) {
+                    fail(e.code, "circuit " + std::to_string(i) + " gate " + std::to_string(g) + ": " + e.what());
+                }
+            }
+        }
+        b->arena_amps = off;
+        const int bpa = bytes_per_amp(enc);
+        size_t free_b = 0, total_b = 0;
+        JQ_HIP(hipMemGetInfo(&free_b, &total_b));
+        if (off * bpa > free_b) fail(JQ_ENOMEM, "jq_batch_create: arena does not fit in device memory");
+        JQ_HIP(hipMalloc(&b->arena, off * bpa));
+        JQ_HIP(hipMalloc(&b->counter, sizeof(uint32_t)));
+        // largest states first: the long jobs start early
+        std::vector<int32_t> order(count);
+        for (size_t i = 0; i < count; ++i) order[i] = (int32_t)i;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return b->n[x] > b->n[y]; });
+        JQ_HIP(hipMalloc(&b->order, count * sizeof(int32_t)));
+        JQ_HIP(hipMemcpy(b->order, order.data(), count * sizeof(int32_t), hipMemcpyHostToDevice));
+        // LDS-resident states up to 64 KiB
+        int lds_n = 0;
+        while (lds_n < 20 && ((size_t)bpa << (lds_n + 1)) <= (size_t)kLdsBytes) ++lds_n;
+        b->lds_max_n = lds_n;
+        b->lds_bytes = (size_t)bpa << lds_n;
+        int dev = 0, cus = 0;
+        JQ_HIP(hipGetDevice(&dev));
+        JQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        int per_cu = 0;
+        const void* kfn = enc == JQ_C128 ? (const void*)k_batch<double> : (const void*)k_batch<float>;
+        JQ_HIP(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes));
+        JQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kBatchThreads, b->lds_bytes));
+        if (per_cu < 1) per_cu = 1;
+        b->grid = std::max(1, std::min<int>((int)count, cus * per_cu));
+        if (stream) {
+            b->stream = (hipStream_t)stream;
+        } else {
+            JQ_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+            b->own_stream = true;
+        }
+        JQ_HIP(hipEventCreate(&b->ev0));
+        JQ_HIP(hipEventCreate(&b->ev1));
+        autotune(b, opts);
+        upload_plans(b);
+        *out = b;
+        return JQ_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        free_batch(b);
+        return e.code;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        free_batch(b);
+        return JQ_EDEVICE;
+    }
+}
+
+int jq_batch_run(jq_batch* b, double* elapsed_ms) {
+    try {
+        set_last_error("");
+        if (!b) fail(JQ_EINVAL, "null batch");
+        if (elapsed_ms) {
+            *elapsed_ms = timed_launch(b);
+        } else {
+            launch(b);
+        }
+        return JQ_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    }
+}
+
+int jq_batch_read(jq_batch* b, size_t index, uint64_t first, uint64_t count, double* out) {
+    try {
+        set_last_error("");
+        if (!b) fail(JQ_EINVAL, "null batch");
+        if (index >= b->count) fail(JQ_EINVAL, "jq_batch_read: index out of range");
+        const uint64_t dim = 1ull << b->n[index];
+        if (first > dim || count > dim - first) fail(JQ_EINVAL, "jq_batch_read: range out of bounds");
+        if (count && !out) fail(JQ_EINVAL, "jq_batch_read: null output");
+        const uint64_t at = b->offs[index] + first;
+        if (b->enc == JQ_C128) {
+            JQ_HIP(hipMemcpyAsync(out, (const double2*)b->arena + at, count * 16, hipMemcpyDeviceToHost, b->stream));
+        } else {
+            double* tmp = nullptr;
+            JQ_HIP(hipMalloc(&tmp, std::max<uint64_t>(count, 1) * 16));
+            sv_to_c128(JQ_C64, b->arena, at, count, tmp, b->stream);
+            JQ_HIP(hipMemcpyAsync(out, tmp, count * 16, hipMemcpyDeviceToHost, b->stream));
+            JQ_HIP(hipStreamSynchronize(b->stream));
+            JQ_HIP(hipFree(tmp));
+        }
+        JQ_HIP(hipStreamSynchronize(b->stream));
+        return JQ_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    }
+}
+
+int jq_batch_destroy(jq_batch* b) {
+    free_batch(b);
+    return JQ_OK;
+}
+
+}  // extern "C"

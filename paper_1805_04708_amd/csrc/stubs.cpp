@@ -3,14 +3,6 @@
 #include "internal.hpp"
 
 extern "C" {
-int jq_batch_create(const jq_circuit*, size_t, jq_encoding, const jq_exec_opts*, void*, jq_batch** out) {
-    if (out) *out = nullptr;
-    jq::set_last_error("batched launch is not built");
-    return JQ_EUNSUPPORTED;
-}
-int jq_batch_run(jq_batch*, double*) { jq::set_last_error("batched launch is not built"); return JQ_EUNSUPPORTED; }
-int jq_batch_read(jq_batch*, size_t, uint64_t, uint64_t, double*) { jq::set_last_error("batched launch is not built"); return JQ_EUNSUPPORTED; }
-int jq_batch_destroy(jq_batch*) { return JQ_EUNSUPPORTED; }
 int jq_server_create(uint64_t, int, int, jq_encoding, jq_server** out) {
     if (out) *out = nullptr;
     jq::set_last_error("server is not built");

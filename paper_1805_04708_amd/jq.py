@@ -296,6 +296,60 @@ class State:
                 for i in range(min(cnt.value, 16))}
 
 
+# -------------------------------------------------------------- batch --
+
+def circuit_struct(n, circuit):
+    """(jq_circuit, keep-alive) for a list of named gates."""
+    arr, cnt = gates(circuit)
+    c = Circuit()
+    c.n_qubits, c.n_gates = n, cnt
+    c.gates = ctypes.cast(arr, ctypes.POINTER(Gate))
+    return c, arr
+
+
+class Batch:
+    """Many small circuits run in one persistent launch (jq_batch_*)."""
+
+    def __init__(self, instances, encoding="c128", fusion=0, stream=None):
+        enc = ENCODINGS[encoding] if isinstance(encoding, str) else int(encoding)
+        self.ns = [int(n) for n, _ in instances]
+        structs = (Circuit * len(instances))()
+        self._keep = []
+        for i, (n, circ) in enumerate(instances):
+            c, arr = circuit_struct(n, circ)
+            structs[i] = c
+            self._keep.append(arr)
+        opts = exec_opts(fusion)
+        h = _VP()
+        handle = getattr(stream, "cuda_stream", stream)
+        check(lib().jq_batch_create(structs, len(instances), enc, ctypes.byref(opts),
+                                    _VP(handle) if handle else None, ctypes.byref(h)))
+        self.h = h
+        self._keep = None
+
+    def run(self, timed=False):
+        ms = ctypes.c_double()
+        check(lib().jq_batch_run(self.h, ctypes.byref(ms) if timed else None))
+        return ms.value if timed else None
+
+    def amplitudes(self, index):
+        dim = 1 << self.ns[index]
+        out = np.zeros(dim, dtype=np.complex128)
+        check(lib().jq_batch_read(self.h, index, 0, dim, _dp(out.view(np.float64))))
+        return out
+
+    def close(self):
+        if self.h:
+            h, self.h = self.h, None
+            check(lib().jq_batch_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ------------------------------------------------------- torch memory --
 
 _ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

@@ -1,0 +1,93 @@
+"""GPU parity of the batched persistent launch (many small circuits in one
+kernel) against the CPU oracle, and batch-vs-alone bitwise equality."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import core as O
+from paper_1805_04708_amd import jq
+from paper_1805_04708_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    jq.lib()
+
+
+def mixed_circuit(n, gates, rng):
+    out = []
+    for _ in range(gates):
+        q = [int(x) for x in rng.permutation(n)]
+        r = rng.random()
+        if r < 0.35 or n < 2:
+            out.append(("MAT1", (q[0],), W.haar_u2(rng)))
+        elif r < 0.5:
+            out.append(("CNOT", (q[0], q[1]), ()))
+        elif r < 0.65:
+            out.append(("CP", (q[0], q[1]), (float(rng.uniform(0, 6)),)))
+        elif r < 0.75:
+            out.append(("RZ", (q[0],), (float(rng.uniform(0, 6)),)))
+        elif r < 0.82:
+            out.append(("SWAP", (q[0], q[1]), ()))
+        elif r < 0.9 and n >= 3:
+            out.append(("TOFFOLI", (q[0], q[1], q[2]), ()))
+        elif n >= 2:
+            out.append(("MAT1", (q[0],), W.haar_u2(rng), (q[1],)))
+    return out
+
+
+def oracle_state(n, circ):
+    return O.run(O.zero_state(n), n, circ)
+
+
+@pytest.mark.parametrize("enc,tol", [("c128", 1e-12), ("c64", 5e-6)])
+@pytest.mark.parametrize("fusion", [0, 1, 2, 3])
+def test_batch_matches_oracle(enc, tol, fusion):
+    rng = np.random.default_rng(17 + fusion)
+    inst = []
+    for i in range(120):
+        n = int(rng.integers(1, 15))
+        inst.append((n, mixed_circuit(n, int(rng.integers(0, 50)), rng)))
+    b = jq.Batch(inst, enc, fusion=fusion)
+    b.run()
+    for i, (n, circ) in enumerate(inst):
+        got = b.amplitudes(i)
+        ref = oracle_state(n, circ)
+        assert O.rel_l2(got, ref) <= tol, (i, n, O.rel_l2(got, ref))
+    b.close()
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+def test_batch_workload_sizes_and_alone_equality(enc):
+    # N in 8..16 with the random 100-gate circuits of the small-circuit workload
+    inst = W.batch_instances(48, base_seed=900)
+    b = jq.Batch(inst, enc)
+    b.run()
+    first = [b.amplitudes(i) for i in range(len(inst))]
+    b.run()  # a second run resets every state and gives identical bits
+    for i in range(len(inst)):
+        assert np.array_equal(first[i], b.amplitudes(i))
+    for i in range(0, len(inst), 6):
+        n, circ = inst[i]
+        ref = oracle_state(n, circ)
+        assert O.rel_l2(first[i], ref) <= (1e-12 if enc == "c128" else 5e-6)
+        alone = jq.Batch([inst[i]], enc)
+        alone.run()
+        assert np.array_equal(alone.amplitudes(i - i), first[i]), i
+        alone.close()
+    b.close()
+
+
+def test_batch_rejects_bad_input():
+    with pytest.raises(jq.JqError):
+        jq.Batch([(21, [])], "c128")
+    with pytest.raises(jq.JqError):
+        jq.Batch([(3, [("H", (3,), ())])], "c128")
+    with pytest.raises(jq.JqError):
+        jq.Batch([(3, [])], "compact")
