@@ -192,6 +192,19 @@ void cp_to_c128(const CompactBufs& b, int n, uint64_t first, uint64_t count, dou
                 hipStream_t st);
 void cp_encode_from_c128(const CompactBufs& b, int n, const double* src, hipStream_t st);
 
+// ---------------------------------------------------- runtime helpers --
+
+// Create a state whose work runs on `stream`.  async_alloc: its device
+// memory comes from the stream-ordered allocator (hipMallocAsync) and is
+// returned with hipFreeAsync, so creating and destroying states never waits
+// for other streams (used by the request loop).
+jq_state* state_create(int n, int enc, hipStream_t stream, bool async_alloc);
+
+// Apply canonical ops to a state (planner + kernels), asynchronously.
+void state_apply(jq_state* s, const std::vector<GateOp>& ops, const jq_exec_opts* opts);
+// Enqueue the FP64 squared norm into pinned host memory (no synchronisation).
+void state_norm_async(jq_state* s, double* pinned_out);
+
 }  // namespace jq
 
 // --------------------------------------------------------------- state --
@@ -208,6 +221,7 @@ struct jq_state {
     void* alloc_ctx = nullptr;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    bool async_alloc = false;
     int device = 0;
     // per-launch timing
     bool profiling = false;

@@ -192,6 +192,17 @@ PlanConfig plan_config(const jq_state* s, const jq_exec_opts* opts) {
 void upload_fops(jq_state* s, const std::vector<FOp>& fops) {
     const size_t bytes = fops.size() * sizeof(FOp);
     if (bytes == 0) return;
+    if (s->async_alloc) {
+        if (bytes > s->plan_dev_bytes) {
+            if (s->plan_dev) JQ_HIP(hipFreeAsync(s->plan_dev, s->stream));
+            s->plan_dev = nullptr;
+            JQ_HIP(hipMallocAsync(&s->plan_dev, bytes, s->stream));
+            s->plan_dev_bytes = bytes;
+        }
+        // pageable source: the runtime stages it before the call returns
+        JQ_HIP(hipMemcpyAsync(s->plan_dev, fops.data(), bytes, hipMemcpyHostToDevice, s->stream));
+        return;
+    }
     if (s->plan_ev) JQ_HIP(hipEventSynchronize(s->plan_ev));
     if (bytes > s->plan_dev_bytes) {
         JQ_HIP(hipStreamSynchronize(s->stream));
@@ -252,6 +263,86 @@ void do_probabilities(jq_state* s, const int* qubits, int nq, double* out_host) 
     JQ_HIP(hipStreamSynchronize(s->stream));
 }
 
+jq_state* state_create(int n, int enc, hipStream_t stream, bool async_alloc) {
+    if (n < 1 || n > JQ_MAX_QUBITS) fail(JQ_EINVAL, "jq_state_create: N must be in [1, 63]");
+    if (enc != JQ_C128 && enc != JQ_C64 && enc != JQ_COMPACT) fail(JQ_EINVAL, "jq_state_create: bad encoding");
+    const int bpa = bytes_per_amp(enc);
+    if (n > 61) fail(JQ_ENOMEM, "jq_state_create: 2^N amplitudes cannot be addressed");
+    const uint64_t bytes = (uint64_t)bpa << n;
+    size_t free_b = 0, total_b = 0;
+    JQ_HIP(hipMemGetInfo(&free_b, &total_b));
+    if (bytes > free_b)
+        fail(JQ_ENOMEM, "jq_state_create: state needs " + std::to_string(bytes) + " bytes, " +
+                            std::to_string(free_b) + " free");
+    auto s = new jq_state();
+    s->n = n;
+    s->enc = enc;
+    s->bytes = bytes;
+    s->async_alloc = async_alloc;
+    JQ_HIP(hipGetDevice(&s->device));
+    if (!async_alloc) {
+        std::lock_guard<std::mutex> lk(g_hooks_mu);
+        s->alloc = g_hooks.alloc;
+        s->release = g_hooks.release;
+        s->alloc_ctx = g_hooks.ctx;
+    }
+    try {
+        if (stream) {
+            s->stream = stream;
+        } else {
+            JQ_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+            s->own_stream = true;
+        }
+        s->aux_doubles = kAuxHead + 16384 + 64;
+        if (async_alloc) {
+            JQ_HIP(hipMallocAsync(&s->buf, bytes, s->stream));
+            JQ_HIP(hipMallocAsync((void**)&s->aux, s->aux_doubles * sizeof(double), s->stream));
+        } else {
+            if (s->alloc) {
+                s->buf = s->alloc(bytes, s->alloc_ctx);
+                if (!s->buf) fail(JQ_ENOMEM, "jq_state_create: allocator returned null");
+            } else {
+                JQ_HIP(hipMalloc(&s->buf, bytes));
+            }
+            JQ_HIP(hipMalloc(&s->aux, s->aux_doubles * sizeof(double)));
+        }
+        if (enc == JQ_COMPACT) cp_init(compact_bufs(s), n, JQ_INIT_ZERO, 0, s->stream);
+        else sv_init(enc, s->buf, n, JQ_INIT_ZERO, 0, s->stream);
+    } catch (...) {
+        if (s->async_alloc) {
+            if (s->buf) (void)hipFreeAsync(s->buf, s->stream);
+            if (s->aux) (void)hipFreeAsync(s->aux, s->stream);
+        } else {
+            if (s->buf) {
+                if (s->release) s->release(s->buf, s->alloc_ctx);
+                else (void)hipFree(s->buf);
+            }
+            if (s->aux) (void)hipFree(s->aux);
+        }
+        if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+        delete s;
+        throw;
+    }
+    return s;
+}
+
+void state_apply(jq_state* s, const std::vector<GateOp>& ops, const jq_exec_opts* opts) {
+    (void)plan_config(s, opts);
+    if (s->enc == JQ_COMPACT) {
+        for (const auto& op : ops) run_single(s, op);
+        return;
+    }
+    apply_ops(s, ops, opts);
+}
+
+void state_norm_async(jq_state* s, double* pinned_out) {
+    const size_t cap = 16384;
+    double* scratch = partials(s, 1 + cap);
+    if (s->enc == JQ_COMPACT) cp_probabilities(compact_bufs(s), s->n, nullptr, 0, scratch, scratch + 1, cap, s->stream);
+    else sv_probabilities(s->enc, s->buf, s->n, nullptr, 0, scratch, scratch + 1, cap, s->stream);
+    JQ_HIP(hipMemcpyAsync(pinned_out, scratch, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+}
+
 }  // namespace jq
 
 using namespace jq;
@@ -278,57 +369,27 @@ int jq_state_create(int n, jq_encoding enc, jq_state** out) {
     return guarded([&] {
         if (!out) fail(JQ_EINVAL, "jq_state_create: null output");
         *out = nullptr;
-        if (n < 1 || n > JQ_MAX_QUBITS) fail(JQ_EINVAL, "jq_state_create: N must be in [1, 63]");
-        if (enc != JQ_C128 && enc != JQ_C64 && enc != JQ_COMPACT) fail(JQ_EINVAL, "jq_state_create: bad encoding");
-        const int bpa = bytes_per_amp(enc);
-        if (n > 61) fail(JQ_ENOMEM, "jq_state_create: 2^N amplitudes cannot be addressed");
-        const uint64_t bytes = (uint64_t)bpa << n;
-        size_t free_b = 0, total_b = 0;
-        JQ_HIP(hipMemGetInfo(&free_b, &total_b));
-        if (bytes > free_b)
-            fail(JQ_ENOMEM, "jq_state_create: state needs " + std::to_string(bytes) + " bytes, " +
-                                std::to_string(free_b) + " free");
-        auto s = new jq_state();
-        s->n = n;
-        s->enc = enc;
-        s->bytes = bytes;
-        JQ_HIP(hipGetDevice(&s->device));
-        {
-            std::lock_guard<std::mutex> lk(g_hooks_mu);
-            s->alloc = g_hooks.alloc;
-            s->release = g_hooks.release;
-            s->alloc_ctx = g_hooks.ctx;
-        }
-        try {
-            if (s->alloc) {
-                s->buf = s->alloc(bytes, s->alloc_ctx);
-                if (!s->buf) fail(JQ_ENOMEM, "jq_state_create: allocator returned null");
-            } else {
-                JQ_HIP(hipMalloc(&s->buf, bytes));
-            }
-            s->aux_doubles = kAuxHead + 16384 + 64;
-            JQ_HIP(hipMalloc(&s->aux, s->aux_doubles * sizeof(double)));
-            JQ_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
-            s->own_stream = true;
-            if (enc == JQ_COMPACT) cp_init(compact_bufs(s), n, JQ_INIT_ZERO, 0, s->stream);
-            else sv_init(enc, s->buf, n, JQ_INIT_ZERO, 0, s->stream);
-        } catch (...) {
-            if (s->buf) {
-                if (s->release) s->release(s->buf, s->alloc_ctx);
-                else (void)hipFree(s->buf);
-            }
-            if (s->aux) (void)hipFree(s->aux);
-            if (s->stream) (void)hipStreamDestroy(s->stream);
-            delete s;
-            throw;
-        }
-        *out = s;
+        *out = state_create(n, enc, nullptr, false);
     });
 }
 
 int jq_state_destroy(jq_state* s) {
     return guarded([&] {
         check_state(s);
+        if (s->async_alloc) {
+            // stream-ordered: memory returns to the pool after the queued work
+            for (auto& r : s->recs) {
+                (void)hipEventDestroy(r.a);
+                (void)hipEventDestroy(r.b);
+            }
+            for (auto ev : s->event_pool) (void)hipEventDestroy(ev);
+            if (s->buf) (void)hipFreeAsync(s->buf, s->stream);
+            if (s->aux) (void)hipFreeAsync(s->aux, s->stream);
+            if (s->plan_dev) (void)hipFreeAsync(s->plan_dev, s->stream);
+            if (s->plan_ev) (void)hipEventDestroy(s->plan_ev);
+            delete s;
+            return;
+        }
         hipError_t e = hipStreamSynchronize(s->stream);
         for (auto& r : s->recs) {
             (void)hipEventDestroy(r.a);

@@ -175,11 +175,16 @@ def exec_opts(fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0):
 # -------------------------------------------------------------- state --
 
 class State:
-    """An N-qubit state on the current HIP device (owns its device memory)."""
+    """An N-qubit state on the current HIP device (owns its device memory,
+    unless it was borrowed from a server result)."""
 
-    def __init__(self, n, encoding="c128"):
+    def __init__(self, n, encoding="c128", handle=None):
         self.n = int(n)
         self.encoding = ENCODINGS[encoding] if isinstance(encoding, str) else int(encoding)
+        self.owned = handle is None
+        if handle is not None:
+            self.h = _VP(handle)
+            return
         h = _VP()
         check(lib().jq_state_create(self.n, self.encoding, ctypes.byref(h)))
         self.h = h
@@ -187,7 +192,8 @@ class State:
     def close(self):
         if self.h:
             h, self.h = self.h, None
-            check(lib().jq_state_destroy(h))
+            if self.owned:
+                check(lib().jq_state_destroy(h))
 
     def __del__(self):
         try:
@@ -342,6 +348,62 @@ class Batch:
         if self.h:
             h, self.h = self.h, None
             check(lib().jq_batch_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ server --
+
+class Server:
+    """Request loop (jq_server_*): circuits of mixed N admitted by state bytes
+    against an HBM budget, run concurrently on several streams."""
+
+    def __init__(self, hbm_budget, n_streams=4, queue_cap=4096, encoding="c64"):
+        self.encoding = ENCODINGS[encoding] if isinstance(encoding, str) else int(encoding)
+        h = _VP()
+        check(lib().jq_server_create(int(hbm_budget), n_streams, queue_cap, self.encoding, ctypes.byref(h)))
+        self.h = h
+
+    def submit(self, n, circuit, blocking=True):
+        """circuit: named gates, or a (Gate array, count) pair from gates()."""
+        arr, cnt = circuit if isinstance(circuit, tuple) else gates(circuit)
+        c = Circuit()
+        c.n_qubits, c.n_gates = int(n), cnt
+        c.gates = ctypes.cast(arr, ctypes.POINTER(Gate))
+        t = _U64()
+        check(lib().jq_server_submit(self.h, ctypes.byref(c), 1 if blocking else 0, ctypes.byref(t)))
+        return t.value
+
+    def wait(self, timeout_ms=-1):
+        """The next finished request as a dict, or None after timeout_ms."""
+        r = Result()
+        rc = lib().jq_server_wait(self.h, int(timeout_ms), ctypes.byref(r))
+        if rc == JQ_EBUSY:
+            return None
+        check(rc)
+        return {"ticket": r.ticket, "status": r.status, "n": r.n_qubits, "norm": r.norm,
+                "latency_ms": r.latency_ms, "queue_ms": r.queue_ms, "state": r.state}
+
+    def state(self, result):
+        """Borrowed view of a finished request's state (valid until release)."""
+        return State(result["n"], self.encoding, handle=result["state"])
+
+    def release(self, ticket):
+        check(lib().jq_server_release(self.h, int(ticket)))
+
+    def stats(self):
+        st = ServerStats()
+        check(lib().jq_server_stats_get(self.h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.h:
+            h, self.h = self.h, None
+            check(lib().jq_server_destroy(h))
 
     def __del__(self):
         try:
