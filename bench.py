@@ -161,6 +161,13 @@ def main():
     state.close()
     torch.cuda.synchronize()
 
+    if not args.no_extras:
+        out["c64_same_circuit"] = c64_same_circuit(n, circuit, args.fusion)
+        out["batch"] = batch_extra()
+        out["serve"] = serve_extra()
+        out["compact"] = compact_extra()
+        out["large_states"] = large_extra()
+
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -178,6 +185,184 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, circuit, args.cpu_gates)
     print(json.dumps(out))
+
+
+def c64_same_circuit(n, circuit, fusion):
+    """The same circuit on a complex64 state (FP32 arithmetic)."""
+    import torch
+    from paper_1805_04708_amd import jq
+
+    s = jq.State(n, "c64").set_stream(torch.cuda.current_stream())
+    arr = jq.gates(circuit)
+    s.apply_circuit(arr, fusion=fusion)
+    s.synchronize()
+    s.init(jq.JQ_INIT_ZERO)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.apply_circuit(arr, fusion=fusion)
+    nrm = s.norm()
+    dt = time.perf_counter() - t0
+    s.close()
+    return {"gates_per_s": len(circuit) / dt, "ms": 1000 * dt, "norm_minus_1": nrm - 1.0}
+
+
+def batch_extra(count=4096, seed=4096):
+    """Many small circuits (N uniform in 8..16, 100 random gates) in one launch."""
+    import numpy as np
+    from oracle import core as O
+    from paper_1805_04708_amd import jq
+    from paper_1805_04708_amd import workloads as W
+
+    inst = W.batch_instances(count, base_seed=seed)
+    res = {"circuits": count, "gates_per_circuit": 100, "n_range": [8, 16]}
+    for enc in ("c128", "c64"):
+        b = jq.Batch(inst, enc)
+        b.run(timed=True)
+        ms = min(b.run(timed=True) for _ in range(3))
+        errs = []
+        for i in range(0, count, count // 16):
+            n, circ = inst[i]
+            ref = O.run(O.zero_state(n), n, circ)
+            errs.append(O.rel_l2(b.amplitudes(i), ref))
+        b.close()
+        res[enc] = {"circuits_per_s": count / (ms * 1e-3), "launch_ms": ms, "max_rel_l2_vs_oracle": max(errs),
+                    "median_rel_l2_vs_oracle": float(np.median(errs)), "checked": len(errs)}
+    return res
+
+
+def serve_extra(count=2000, seed=77, enc="c64"):
+    """Poisson arrivals of layered circuits, N in 10..28 with weight 2^(-N/2),
+    depth 20..200: the request loop vs the plain one-at-a-time path."""
+    import numpy as np
+    import torch
+    from paper_1805_04708_amd import jq
+    from paper_1805_04708_amd import workloads as W
+
+    probe = W.serving_trace(200, 1.0, seed + 1)
+    lowered = [(n, jq.gates(c)) for _, n, c in probe]
+    # service rate of the plain path: unfused per-gate kernels, one stream
+    t0 = time.perf_counter()
+    for n, arr in lowered:
+        with jq.State(n, enc) as s:
+            s.apply_circuit(arr, fusion=1)
+            s.norm()
+    mean_service = (time.perf_counter() - t0) / len(lowered)
+    rate = 0.9 / mean_service
+    trace = W.serving_trace(count, rate, seed)
+    reqs = [(t, n, jq.gates(c)) for t, n, c in trace]
+
+    # plain path: each request waits for the previous one
+    lat_seq = []
+    start = time.perf_counter()
+    for t, n, arr in reqs:
+        now = time.perf_counter() - start
+        if now < t:
+            time.sleep(t - now)
+        with jq.State(n, enc) as s:
+            s.apply_circuit(arr, fusion=1)
+            s.norm()
+        lat_seq.append(1000 * (time.perf_counter() - start - t))
+    seq_span = time.perf_counter() - start
+
+    sv = jq.Server(hbm_budget=280 << 30, n_streams=4, queue_cap=count, encoding=enc)
+    import threading
+    lat, lags = [], []
+
+    def drain():
+        for _ in reqs:
+            r = sv.wait(120000)
+            if r is None:
+                return
+            lat.append(r["latency_ms"])
+            sv.release(r["ticket"])
+
+    th = threading.Thread(target=drain)
+    th.start()
+    start = time.perf_counter()
+    for t, n, arr in reqs:
+        now = time.perf_counter() - start
+        if now < t:
+            time.sleep(t - now)
+        lags.append(1000 * max(0.0, time.perf_counter() - start - t))
+        sv.submit(n, arr)
+    th.join()
+    span = time.perf_counter() - start
+    st = sv.stats()
+    sv.close()
+    lat_all = np.array(lat) + np.array(lags[:len(lat)])
+    return {"requests": count, "encoding": enc, "arrival_rate_per_s": rate,
+            "served": {"p50_ms": float(np.percentile(lat_all, 50)), "p99_ms": float(np.percentile(lat_all, 99)),
+                       "throughput_per_s": count / span, "peak_resident_bytes": st["peak_resident_bytes"]},
+            "sequential_plain": {"p50_ms": float(np.percentile(lat_seq, 50)),
+                                 "p99_ms": float(np.percentile(lat_seq, 99)), "throughput_per_s": count / seq_span},
+            "note": "latency = arrival to device completion; the plain path runs one circuit at a time "
+                    "with one kernel per gate"}
+
+
+def compact_extra(n=30, layers=20):
+    """The RZ + CNOT-chain circuit from the uniform state in the two-byte code,
+    gate by gate quantisation; fidelity against the complex128 result of the
+    same circuit on this GPU."""
+    import numpy as np
+    from paper_1805_04708_amd import jq
+    from paper_1805_04708_amd import workloads as W
+
+    circ = W.rz_cnot_chain(n, layers, seed=34)
+    arr = jq.gates(circ)
+    cp = jq.State(n, "compact").init(jq.JQ_INIT_UNIFORM)
+    cp.apply_circuit(arr)
+    cp.synchronize()
+    cp.init(jq.JQ_INIT_UNIFORM)
+    cp.synchronize()
+    t0 = time.perf_counter()
+    cp.apply_circuit(arr)
+    cp.synchronize()
+    dt = time.perf_counter() - t0
+    ref = jq.State(n, "c128").init(jq.JQ_INIT_UNIFORM)
+    ref.apply_circuit(arr)
+    ov, nr, nc = 0j, 0.0, 0.0
+    chunk = 1 << 24
+    for first in range(0, 1 << n, chunk):
+        a = cp.amplitudes(first, chunk)
+        b = ref.amplitudes(first, chunk)
+        ov += np.vdot(b, a)
+        nr += float(np.vdot(b, b).real)
+        nc += float(np.vdot(a, a).real)
+    diff2 = nc + nr - 2 * ov.real
+    cp.close()
+    ref.close()
+    return {"n": n, "gates": len(circ), "gates_per_s": len(circ) / dt, "seconds": dt,
+            "fidelity_vs_c128": abs(ov) ** 2 / (nr * nc), "rel_l2_vs_c128": float(np.sqrt(max(diff2, 0) / nr))}
+
+
+def large_extra():
+    """One layer of the RZ + CNOT-chain circuit on 256 GiB states: N=34
+    complex128 and N=37 two-byte code, from the uniform state."""
+    from paper_1805_04708_amd import jq
+    from paper_1805_04708_amd import workloads as W
+
+    out = {}
+    for n, enc in ((34, "c128"), (37, "compact")):
+        try:
+            s = jq.State(n, enc).init(jq.JQ_INIT_UNIFORM)
+        except Exception as e:  # not enough HBM on this device
+            out[f"{enc}_n{n}"] = {"error": str(e)}
+            continue
+        circ = W.rz_cnot_chain(n, 1, seed=n)
+        arr = jq.gates(circ)
+        s.synchronize()
+        s.profile(True)
+        t0 = time.perf_counter()
+        s.apply_circuit(arr)
+        nrm = s.norm()
+        dt = time.perf_counter() - t0
+        st = s.profile_read()
+        s.close()
+        out[f"{enc}_n{n}"] = {"gates": len(circ), "seconds": dt, "gates_per_s": len(circ) / dt,
+                              "norm_minus_1": nrm - 1.0, "state_gib": (16 if enc == "c128" else 2) * 2 ** n / 2 ** 30,
+                              "kernels": {k: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"],
+                                              "gbps": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in st.items()}}
+    return out
 
 
 def per_target(state, n, bpa):

@@ -16,7 +16,8 @@
 // when no modulus lies strictly inside (0, 1)); k_cp_gate in apply mode
 // decodes with the old range, applies, and encodes with the new one.
 // Permutations swap code pairs; modulus-preserving diagonal gates rewrite
-// the phase codes of the touched amplitudes only.
+// the phase codes of the touched amplitudes only, by an integer shift of
+// the code unless the shift is a half-integer.
 //
 // This file is compiled with -ffp-contract=off: each product and sum
 // rounds on its own, in the order written, so the codes do not depend on
@@ -179,24 +180,10 @@ __global__ void k_cp_acc_reset(unsigned long long* acc) {
     }
 }
 
-// Permutation fast path: exchange the code pairs of amplitudes that differ
-// in the target bit, inside the controlled subspace.
-__global__ __launch_bounds__(kBlock) void k_cp_permx(int8_t* __restrict__ b0, int8_t* __restrict__ b1,
-                                                      uint64_t ngroups, Ins ins, uint64_t tbit) {
-    for (uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x; gi < ngroups;
-         gi += (uint64_t)gridDim.x * kBlock) {
-        const uint64_t i = expand(gi, ins), j = i | tbit;
-        const int8_t x0 = b0[i], x1 = b1[i], y0 = b0[j], y1 = b1[j];
-        b0[i] = y0;
-        b1[i] = y1;
-        b0[j] = x0;
-        b1[j] = x1;
-    }
-}
-
-// Modulus-preserving diagonal fast path: only the phase codes of the
-// touched amplitudes change (the range is kept, so the modulus code of a
-// decoded-and-rotated amplitude encodes back to itself).
+// Modulus-preserving diagonal gate whose phase shift sits on a rounding
+// tie: decode, rotate and re-encode the phase of each touched amplitude
+// (the range is kept, so the modulus code of a decoded-and-rotated
+// amplitude encodes back to itself).
 __global__ __launch_bounds__(kBlock) void k_cp_phase(const int8_t* __restrict__ b0, int8_t* __restrict__ b1,
                                                       uint64_t ngroups, Ins ins, CpGate g,
                                                       const double* __restrict__ rng) {
@@ -287,6 +274,139 @@ struct LoaderCP {
     }
 };
 
+// ------------------------------------------------------ chunked forms --
+//
+// When every fixed index bit of a gate (target, controls) lies at position
+// log2(W) or above, W consecutive codes of a plane belong to W consecutive
+// groups, so a thread moves them with one 4- or 16-byte access.
+
+template <int W>
+struct Codes {
+    int8_t v[W];
+};
+
+template <int W>
+__device__ __forceinline__ Codes<W> ldc(const int8_t* p, uint64_t i) {
+    Codes<W> c;
+    if constexpr (W == 16) {
+        const uint4 x = *reinterpret_cast<const uint4*>(p + i);
+        __builtin_memcpy(c.v, &x, 16);
+    } else if constexpr (W == 4) {
+        const uint32_t x = *reinterpret_cast<const uint32_t*>(p + i);
+        __builtin_memcpy(c.v, &x, 4);
+    } else {
+        c.v[0] = p[i];
+    }
+    return c;
+}
+
+template <int W>
+__device__ __forceinline__ void stc(int8_t* p, uint64_t i, const Codes<W>& c) {
+    if constexpr (W == 16) {
+        uint4 x;
+        __builtin_memcpy(&x, c.v, 16);
+        *reinterpret_cast<uint4*>(p + i) = x;
+    } else if constexpr (W == 4) {
+        uint32_t x;
+        __builtin_memcpy(&x, c.v, 4);
+        *reinterpret_cast<uint32_t*>(p + i) = x;
+    } else {
+        p[i] = c.v[0];
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_cp_permx_w(int8_t* __restrict__ b0, int8_t* __restrict__ b1,
+                                                        uint64_t nchunks, Ins ins, uint64_t tbit) {
+    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < nchunks; c += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i = expand(c * W, ins), j = i | tbit;
+        const Codes<W> x0 = ldc<W>(b0, i), x1 = ldc<W>(b1, i), y0 = ldc<W>(b0, j), y1 = ldc<W>(b1, j);
+        stc<W>(b0, i, y0);
+        stc<W>(b1, i, y1);
+        stc<W>(b0, j, x0);
+        stc<W>(b1, j, x1);
+    }
+}
+
+struct Shift {
+    double d[4];  // phase of each diagonal entry in code units, 128 arg(d)/pi
+};
+
+// Modulus-preserving diagonal gate: the phase code moves by the entry's
+// phase in code units, rounded half to even and wrapped to [-128, 128).
+// This is the code the decode-multiply-encode step produces, except where
+// b1 + shift lies within a few ulps of a half-integer (a rounding tie, where
+// either neighbour is a correct rounding).  Zero amplitudes keep code 0.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_cp_shift_w(const int8_t* __restrict__ b0, int8_t* __restrict__ b1,
+                                                        uint64_t nchunks, Ins ins, int nsel, int s0, int s1,
+                                                        Shift sh) {
+    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < nchunks; c += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i = expand(c * W, ins);
+        const Codes<W> m = ldc<W>(b0, i);
+        Codes<W> p = ldc<W>(b1, i);
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+            const uint64_t idx = i + u;
+            int sel = 0;
+            if (nsel >= 1) sel = (int)((idx >> s0) & 1);
+            if (nsel == 2) sel = 2 * sel + (int)((idx >> s1) & 1);
+            double dv = sh.d[0];
+            dv = sel == 1 ? sh.d[1] : dv;
+            dv = sel == 2 ? sh.d[2] : dv;
+            dv = sel == 3 ? sh.d[3] : dv;
+            int t = (int)rint((double)p.v[u] + dv);
+            t = ((t + 128) & 255) - 128;
+            p.v[u] = m.v[u] == -128 ? (int8_t)0 : (int8_t)t;
+        }
+        stc<W>(b1, i, p);
+    }
+}
+
+// Dense single-qubit gate over all pairs (target bit t, W <= 2^t), range or
+// apply mode as in k_cp_gate.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_cp_dense1_w(int8_t* __restrict__ b0, int8_t* __restrict__ b1,
+                                                         uint64_t nchunks, Ins ins, uint64_t tbit, CpGate g,
+                                                         const double* __restrict__ rng_old,
+                                                         const double* __restrict__ rng_new,
+                                                         unsigned long long* __restrict__ acc, int apply) {
+    const Range ro{rng_old[0], rng_old[1]};
+    Range rn = ro;
+    if (apply) rn = Range{rng_new[0], rng_new[1]};
+    double lo = 2.0, hi = 0.0;
+    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < nchunks; c += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i = expand(c * W, ins), j = i | tbit;
+        Codes<W> x0 = ldc<W>(b0, i), x1 = ldc<W>(b1, i), y0 = ldc<W>(b0, j), y1 = ldc<W>(b1, j);
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+            const Cx<double> z0 = decode(x0.v[u], x1.v[u], ro), z1 = decode(y0.v[u], y1.v[u], ro);
+            const bool on = ((i + u) & g.cmask) == g.cmask;
+            Cx<double> w0 = cadd(cmul(g.m[0], z0), cmul(g.m[1], z1));
+            Cx<double> w1 = cadd(cmul(g.m[2], z0), cmul(g.m[3], z1));
+            w0 = on ? w0 : z0;
+            w1 = on ? w1 : z1;
+            if (!apply) {
+                range_update(modulus(w0), lo, hi);
+                range_update(modulus(w1), lo, hi);
+            } else {
+                const int c0 = encode_mod(modulus(w0), rn), c1 = encode_mod(modulus(w1), rn);
+                x0.v[u] = (int8_t)c0;
+                x1.v[u] = (int8_t)(c0 == -128 ? 0 : encode_phase(w0));
+                y0.v[u] = (int8_t)c1;
+                y1.v[u] = (int8_t)(c1 == -128 ? 0 : encode_phase(w1));
+            }
+        }
+        if (apply) {
+            stc<W>(b0, i, x0);
+            stc<W>(b1, i, x1);
+            stc<W>(b0, j, y0);
+            stc<W>(b1, j, y1);
+        }
+    }
+    if (!apply) range_flush(lo, hi, acc);
+}
+
 // ------------------------------------------------------------ launchers --
 
 namespace {
@@ -312,6 +432,15 @@ unsigned persistent_blocks(uint64_t items) {
     uint64_t b = (items + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
     return (unsigned)(b < 16384 ? b : 16384);
+}
+
+// widest chunk (16, 4 or 1 codes) whose index bits hold no fixed bit and
+// that fits in the ng groups
+int chunk_width(uint64_t fixed_bits, uint64_t ng) {
+    const int low = fixed_bits ? __builtin_ctzll(fixed_bits) : 64;
+    int w = low >= 4 ? 16 : low >= 2 ? 4 : 1;
+    while ((uint64_t)w > ng) w /= 4;
+    return w < 1 ? 1 : w;
 }
 
 CpGate to_cp(const GateOp& op) {
@@ -345,16 +474,50 @@ void cp_apply_op(const CompactBufs& b, int n, const GateOp& op, hipStream_t st) 
     unsigned long long* acc = (unsigned long long*)b.acc;
     if (op.kind == OP_PERMX) {
         const uint64_t tb = 1ull << op.t0;
+        const uint64_t fixed = op.cmask | tb;
         const uint64_t ng = 1ull << (n - 1 - __builtin_popcountll(op.cmask));
-        hipLaunchKernelGGL(k_cp_permx, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng,
-                           make_ins(op.cmask | tb, op.cmask), tb);
+        const Ins ins = make_ins(fixed, op.cmask);
+        const int w = chunk_width(fixed, ng);
+        if (w == 16)
+            hipLaunchKernelGGL(k_cp_permx_w<16>, dim3(persistent_blocks(ng / 16)), dim3(kBlock), 0, st, b0, b1,
+                               ng / 16, ins, tb);
+        else if (w == 4)
+            hipLaunchKernelGGL(k_cp_permx_w<4>, dim3(persistent_blocks(ng / 4)), dim3(kBlock), 0, st, b0, b1, ng / 4,
+                               ins, tb);
+        else
+            hipLaunchKernelGGL(k_cp_permx_w<1>, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng, ins, tb);
         JQ_HIP(hipGetLastError());
         return;
     }
     if (op.kind == OP_DIAG && op.keeps_modulus) {
         const uint64_t ng = 1ull << (n - __builtin_popcountll(op.cmask));
-        hipLaunchKernelGGL(k_cp_phase, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng,
-                           make_ins(op.cmask, op.cmask), to_cp(op), (const double*)b.range);
+        const Ins ins = make_ins(op.cmask, op.cmask);
+        Shift sh{};
+        bool near_tie = false;
+        for (int i = 0; i < 4; ++i) {
+            sh.d[i] = (128.0 * std::atan2(op.m[i].im, op.m[i].re)) / kPiD;
+            const double f = sh.d[i] - std::floor(sh.d[i]);
+            near_tie |= std::fabs(f - 0.5) < 1e-6;
+        }
+        if (near_tie) {
+            // the shift puts every code on a rounding tie: decode, rotate and
+            // re-encode each amplitude so the tie is broken by its own value
+            hipLaunchKernelGGL(k_cp_phase, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng, ins,
+                               to_cp(op), (const double*)b.range);
+            JQ_HIP(hipGetLastError());
+            return;
+        }
+        const int w = chunk_width(op.cmask, ng);
+        const int s0 = op.t0 < 0 ? 0 : op.t0, s1 = op.t1 < 0 ? 0 : op.t1;
+        if (w == 16)
+            hipLaunchKernelGGL(k_cp_shift_w<16>, dim3(persistent_blocks(ng / 16)), dim3(kBlock), 0, st, b0, b1,
+                               ng / 16, ins, op.nsel, s0, s1, sh);
+        else if (w == 4)
+            hipLaunchKernelGGL(k_cp_shift_w<4>, dim3(persistent_blocks(ng / 4)), dim3(kBlock), 0, st, b0, b1, ng / 4,
+                               ins, op.nsel, s0, s1, sh);
+        else
+            hipLaunchKernelGGL(k_cp_shift_w<1>, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng, ins,
+                               op.nsel, s0, s1, sh);
         JQ_HIP(hipGetLastError());
         return;
     }
@@ -363,10 +526,18 @@ void cp_apply_op(const CompactBufs& b, int n, const GateOp& op, hipStream_t st) 
     Ins ins{};
     auto launch = [&](int apply) {
         const double* rn = b.range_next;
+        const int w = op.kind == OP_DENSE1 ? chunk_width(lb, ng) : 1;
         switch (op.kind) {
             case OP_DENSE1:
-                hipLaunchKernelGGL(k_cp_gate<OP_DENSE1>, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng,
-                                   ins, hb, lb, g, (const double*)b.range, rn, acc, apply);
+                if (w == 16)
+                    hipLaunchKernelGGL(k_cp_dense1_w<16>, dim3(persistent_blocks(ng / 16)), dim3(kBlock), 0, st, b0,
+                                       b1, ng / 16, ins, lb, g, (const double*)b.range, rn, acc, apply);
+                else if (w == 4)
+                    hipLaunchKernelGGL(k_cp_dense1_w<4>, dim3(persistent_blocks(ng / 4)), dim3(kBlock), 0, st, b0, b1,
+                                       ng / 4, ins, lb, g, (const double*)b.range, rn, acc, apply);
+                else
+                    hipLaunchKernelGGL(k_cp_dense1_w<1>, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng,
+                                       ins, lb, g, (const double*)b.range, rn, acc, apply);
                 break;
             case OP_DENSE2:
                 hipLaunchKernelGGL(k_cp_gate<OP_DENSE2>, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng,
