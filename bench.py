@@ -42,8 +42,20 @@ def parse():
     return p.parse_args()
 
 
+KERNEL_SOURCES = ["kernels_sv.hip", "device_common.hpp", "internal.hpp", "planner.cpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1805_04708_amd", "csrc")
+    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in KERNEL_SOURCES)
+    return hashlib.sha256(data).hexdigest()[:16]
+
+
 def traffic_from_profiles(kernel, workload):
-    """HBM bytes per launch measured with rocprofv3 counters, if recorded."""
+    """HBM bytes per launch from the recorded rocprofv3 FETCH_SIZE/WRITE_SIZE
+    runs (scaled by the copy-kernel calibration), or None if there is no
+    record or the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -51,7 +63,7 @@ def traffic_from_profiles(kernel, workload):
         rec = json.load(open(path)).get(f"{kernel}:{workload}")
     except Exception:
         return None
-    if not rec:
+    if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
 

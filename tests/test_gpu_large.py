@@ -1,0 +1,125 @@
+"""GPU checks at the workload sizes: the 30-qubit complex128 layered circuit in
+the benchmark's launch configuration, and 256 GiB states (N=34 complex128,
+N=37 two-byte code).  The oracle cannot hold these states, so the checks use
+outputs it can compute one by one (product-state amplitudes through its own
+gate table) and properties that hold at any size (a circuit followed by its
+inverse returns |0...0>, norms, closed-form GHZ and uniform states)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gates as OG
+from paper_1805_04708_amd import jq
+from paper_1805_04708_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    jq.lib()
+
+
+def free_gib():
+    import torch
+    return torch.cuda.mem_get_info()[0] / 2 ** 30
+
+
+def inverse(circ):
+    """Inverse circuit: reversed order, each explicit matrix conjugate-transposed."""
+    out = []
+    for g in reversed(circ):
+        name, q, p = g[0], g[1], g[2]
+        if name == "MAT1":
+            m = OG.matrix("MAT1", p).conj().T
+            flat = np.empty(8)
+            flat[0::2], flat[1::2] = m.real.ravel(), m.imag.ravel()
+            out.append(("MAT1", q, tuple(flat)))
+        elif name == "CZ":
+            out.append(g)
+        else:
+            raise ValueError(name)
+    return out
+
+
+def test_n30_layer_amplitudes_one_by_one():
+    # one layer from |0...0>: a product state times the CZ signs, so every
+    # amplitude is prod_q U_q[b_q, 0] * (-1)^(sum over CZ pairs b_a b_b)
+    n = 30
+    circ = W.layered_u2_cz(n, 1, seed=2018)
+    us = {g[1][0]: OG.matrix("MAT1", g[2]) for g in circ if g[0] == "MAT1"}
+    pairs = [g[1] for g in circ if g[0] == "CZ"]
+    rng = np.random.default_rng(1)
+    samples = [0, (1 << n) - 1] + [int(x) for x in rng.integers(0, 1 << n, 200)]
+    with jq.State(n, "c128") as s:
+        s.apply_circuit(circ)
+        for i in samples:
+            bits = [(i >> q) & 1 for q in range(n)]
+            ref = 1.0 + 0j
+            for q in range(n):
+                ref *= us[q][bits[q], 0]
+            for a, b in pairs:
+                if bits[a] and bits[b]:
+                    ref = -ref
+            got = s.amplitudes(i, 1)[0]
+            assert abs(got - ref) <= 1e-12 * max(abs(ref), 2.0 ** (-n / 2)), (i, got, ref)
+        assert abs(s.norm() - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("enc,tol", [("c128", 1e-11), ("c64", 2e-4)])
+def test_n30_circuit_then_inverse_returns_to_zero_state(enc, tol):
+    n, layers = 30, 6
+    circ = W.layered_u2_cz(n, layers, seed=7)
+    with jq.State(n, enc) as s:
+        s.apply_circuit(circ)
+        mid = s.norm()
+        s.apply_circuit(inverse(circ))
+        a0 = s.amplitudes(0, 1)[0]
+        assert abs(mid - 1.0) < tol
+        assert abs(a0 - 1.0) < tol, a0
+        p = s.probabilities([0, n - 1])
+        assert abs(p[0] - 1.0) < tol
+
+
+def test_n34_c128_uniform_and_ghz():
+    n = 34
+    if free_gib() < 257:
+        pytest.skip("needs 256 GiB of free HBM")
+    with jq.State(n, "c128") as s:
+        s.apply_circuit(W.hadamard_all(n))
+        amp = 2.0 ** (-n / 2)
+        for i in [0, 1, (1 << n) - 1, 123456789]:
+            assert abs(s.amplitudes(i, 1)[0] - amp) < 1e-15
+        assert abs(s.norm() - 1.0) < 1e-12
+        assert np.allclose(s.probabilities([n - 1]), [0.5, 0.5], atol=1e-12)
+        s.init(jq.JQ_INIT_ZERO)
+        s.apply_circuit(W.ghz(n))
+        h = 1 / math.sqrt(2)
+        assert abs(s.amplitudes(0, 1)[0] - h) < 1e-15
+        assert abs(s.amplitudes((1 << n) - 1, 1)[0] - h) < 1e-15
+        assert s.amplitudes(1 << 20, 1)[0] == 0
+        assert np.allclose(s.probabilities([0, 17, n - 1]), [0.5, 0, 0, 0, 0, 0, 0, 0.5], atol=1e-12)
+
+
+def test_n37_two_byte_code_ghz_and_phases():
+    n = 37
+    if free_gib() < 257:
+        pytest.skip("needs 256 GiB of free HBM")
+    with jq.State(n, "compact") as s:
+        s.apply_circuit(W.ghz(n))
+        h = 1 / math.sqrt(2)
+        a = s.amplitudes(0, 1)[0], s.amplitudes((1 << n) - 1, 1)[0]
+        assert abs(a[0] - h) < 1e-15 and abs(a[1] - h) < 1e-15
+        b0, b1, rng = s.codes((1 << n) - 4, 4)
+        assert list(b0) == [-128, -128, -128, -127] and rng[0] == rng[1]
+        assert abs(s.norm() - 1.0) < 1e-14
+        # uniform state, one layer of RZ and the CNOT chain: moduli never change
+        s.init(jq.JQ_INIT_UNIFORM)
+        s.apply_circuit(W.rz_cnot_chain(n, 1, seed=5))
+        b0, b1, rng = s.codes(0, 1 << 12)
+        assert np.all(b0 == -127) and abs(rng[0] - 2.0 ** (-n / 2)) < 1e-30
+        assert abs(s.norm() - 1.0) < 1e-13
