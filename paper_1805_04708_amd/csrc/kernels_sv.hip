@@ -468,35 +468,11 @@ __device__ __forceinline__ void st_stream(typename Vec<R>::T* p, uint64_t i, Cx<
 #endif
 }
 
-template <typename R, int K, int F>
-__global__ __launch_bounds__(kBlock) void k_fused(typename Vec<R>::T* __restrict__ psi, FPass P) {
-    constexpr int S = 1 << K;
-    const int lane = threadIdx.x & 63;
-    const uint64_t waves_per_block = blockDim.x >> 6;
-    const uint64_t wave = (uint64_t)blockIdx.x * waves_per_block +
-                          (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint64_t o = wave;
-    for (int i = 0; i < P.n_tile; ++i) {
-        const int p = P.tile_sorted[i];
-        o = ((o >> p) << (p + 1)) | (o & ((1ull << p) - 1));
-    }
-    uint64_t base = o | (uint64_t)(lane & ((1 << F) - 1));
-#pragma unroll
-    for (int b = F; b < 6; ++b) base |= (uint64_t)((lane >> b) & 1) << P.lane_q[b];
-    uint64_t stride[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) stride[j] = 1ull << P.reg_q[j];
-    Cx<R> a[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        uint64_t off = 0;
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (s & (1 << j)) off += stride[j];
-        a[s] = ld_stream<R>(psi, base + off);
-    }
-    for (int k = 0; k < P.n_ops; ++k) {
-        const FOp* op = P.ops + k;
+template <typename R, int K>
+__device__ __forceinline__ void run_ops(Cx<R> (&a)[1 << K], const FOp* __restrict__ ops, int n_ops, uint64_t base,
+                                        int lane) {
+    for (int k = 0; k < n_ops; ++k) {
+        const FOp* op = ops + k;
         const bool thr_ok = (base & op->thr_ctrl) == op->thr_ctrl;
         switch (op->kind) {
             case F_DENSE_REG:
@@ -536,6 +512,45 @@ __global__ __launch_bounds__(kBlock) void k_fused(typename Vec<R>::T* __restrict
                 break;
         }
     }
+}
+
+// Index of lane `lane`'s first amplitude in tile w: the tile number fills
+// the index bits outside the tile, the lane number the lane bits.
+__device__ __forceinline__ uint64_t tile_base(const FPass& P, uint64_t w, uint64_t lane_off) {
+    uint64_t o = w;
+    for (int i = 0; i < P.n_tile; ++i) {
+        const int p = P.tile_sorted[i];
+        o = ((o >> p) << (p + 1)) | (o & ((1ull << p) - 1));
+    }
+    return o | lane_off;
+}
+
+// One tile per wavefront.
+template <typename R, int K, int F>
+__global__ __launch_bounds__(kBlock) void k_fused(typename Vec<R>::T* __restrict__ psi, FPass P,
+                                                   const FOp* __restrict__ ops) {
+    constexpr int S = 1 << K;
+    const int lane = threadIdx.x & 63;
+    const uint64_t waves_per_block = blockDim.x >> 6;
+    const uint64_t wave = (uint64_t)blockIdx.x * waves_per_block +
+                          (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint64_t lane_off = (uint64_t)(lane & ((1 << F) - 1));
+#pragma unroll
+    for (int b = F; b < 6; ++b) lane_off |= (uint64_t)((lane >> b) & 1) << P.lane_q[b];
+    uint64_t base = tile_base(P, wave, lane_off);
+    uint64_t stride[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) stride[j] = 1ull << P.reg_q[j];
+    Cx<R> a[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        uint64_t off = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (s & (1 << j)) off += stride[j];
+        a[s] = ld_stream<R>(psi, base + off);
+    }
+    run_ops<R, K>(a, ops, P.n_ops, base, lane);
     // recompute the store addresses instead of keeping 2^K of them live
     asm volatile("" : "+v"(base));
 #pragma unroll
@@ -709,7 +724,7 @@ template <typename R, int K, int F>
 void launch_fused(typename Vec<R>::T* psi, int n, const FPass& p, hipStream_t st) {
     const uint64_t waves = 1ull << (n - 6 - K);
     const uint64_t wpb = waves < 4 ? waves : 4;
-    hipLaunchKernelGGL((k_fused<R, K, F>), dim3(blocks_for(waves, wpb)), dim3(64 * wpb), 0, st, psi, p);
+    hipLaunchKernelGGL((k_fused<R, K, F>), dim3(blocks_for(waves, wpb)), dim3(64 * wpb), 0, st, psi, p, p.ops);
     JQ_HIP(hipGetLastError());
 }
 

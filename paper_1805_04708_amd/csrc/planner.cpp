@@ -211,6 +211,73 @@ void absorb_diagonals(std::vector<PassOp>& ops, uint64_t reg_bits) {
     }
 }
 
+uint64_t sel_mask(const PassOp& p) {
+    uint64_t m = 0;
+    for (int i = 0; i < p.nsel; ++i) m |= 1ull << p.sel[i];
+    return m;
+}
+
+// Every qubit an op reads or changes: target(s), controls, diagonal
+// selectors, multiplexer selectors.
+uint64_t involved(const PassOp& p) { return p.op.support() | sel_mask(p); }
+
+// b after a on the same target (both uncontrolled dense): one multiplexed
+// 2x2 whose matrix for selector value v is B(v) A(v).  False if the union of
+// their selectors has more than two bits.
+bool merge_into(PassOp& b, const PassOp& a) {
+    int sel[2] = {b.sel[0], b.sel[1]};
+    int nsel = b.nsel;
+    for (int i = 0; i < a.nsel; ++i) {
+        const int q = a.sel[i];
+        if ((nsel >= 1 && sel[0] == q) || (nsel == 2 && sel[1] == q)) continue;
+        if (nsel == 2) return false;
+        sel[nsel++] = q;
+    }
+    cd mats[4][4];
+    for (int v = 0; v < (1 << nsel); ++v) {
+        uint64_t idx = 0;
+        for (int i = 0; i < nsel; ++i)
+            if ((v >> (nsel - 1 - i)) & 1) idx |= 1ull << sel[i];
+        int va = 0, vb = 0;
+        for (int i = 0; i < a.nsel; ++i) va = 2 * va + (int)((idx >> a.sel[i]) & 1);
+        for (int i = 0; i < b.nsel; ++i) vb = 2 * vb + (int)((idx >> b.sel[i]) & 1);
+        const cd* A = a.mats[va];
+        const cd* B = b.mats[vb];
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) {
+                const cd x = cmulh(B[2 * r], A[c]), y = cmulh(B[2 * r + 1], A[2 + c]);
+                mats[v][2 * r + c] = {x.re + y.re, x.im + y.im};
+            }
+    }
+    b.nsel = nsel;
+    b.sel[0] = sel[0];
+    b.sel[1] = sel[1];
+    std::memcpy(b.mats, mats, sizeof(mats));
+    return true;
+}
+
+// Merge each uncontrolled dense op into the next uncontrolled dense op on
+// the same target when every op in between leaves the target and the
+// first op's selectors alone (then the first op commutes with all of them).
+void merge_same_target(std::vector<PassOp>& ops) {
+    for (size_t i = 0; i < ops.size(); ++i) {
+        PassOp& a = ops[i];
+        if (!absorbable(a)) continue;
+        const int t = a.op.t0;
+        const uint64_t tb = 1ull << t, sa = sel_mask(a);
+        for (size_t j = i + 1; j < ops.size(); ++j) {
+            PassOp& c = ops[j];
+            if (!c.alive) continue;
+            if (absorbable(c) && c.op.t0 == t) {
+                if (merge_into(c, a)) a.alive = false;
+                break;
+            }
+            if (involved(c) & tb) break;
+            if (c.op.kind != OP_DIAG && (sa & (1ull << c.op.t0))) break;
+        }
+    }
+}
+
 }  // namespace
 
 Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
@@ -313,7 +380,10 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
         }
         uint64_t reg_bits = 0;
         for (int j = 0; j < K; ++j) reg_bits |= 1ull << p.reg_q[j];
-        if (cfg.absorb) absorb_diagonals(pops, reg_bits);
+        if (cfg.absorb) {
+            absorb_diagonals(pops, reg_bits);
+            merge_same_target(pops);
+        }
         int n_ops = 0;
         for (auto& po : pops) {
             if (!po.alive) continue;
