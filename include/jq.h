@@ -95,8 +95,11 @@ typedef struct {
  *  fusion:      0 = let the planner fuse gates into register-blocked tile
  *               passes with its tuned width; 1 = one kernel per gate;
  *               k >= 2 = fuse with at most k register qubits per pass.
- *  compact_mode: a jq_compact_mode, used for JQ_COMPACT states.
- *  max_ops:     upper bound on gates per fused pass (0 = default). */
+ *  compact_mode: a jq_compact_mode, used for JQ_COMPACT states.  In
+ *               PER_BLOCK mode a block is one fused pass (or one gate
+ *               the planner leaves unfused); JQ_EINVAL for other values.
+ *  max_ops:     upper bound on gates per fused pass (0 = default).
+ * jq_plan_schedule reports the blocks a circuit will run as. */
 typedef struct {
     int32_t fusion;
     int32_t compact_mode;
@@ -165,6 +168,20 @@ int jq_apply_gate(jq_state *s, int kind, const int *qubits, int nq, const int *c
  * (see jq_exec_opts); the result equals applying them one by one up to
  * floating-point rounding.  Asynchronous. */
 int jq_apply_circuit(jq_state *s, const jq_gate *gates, size_t count, const jq_exec_opts *opts);
+
+/* The schedule jq_apply_circuit follows for these gates on an N-qubit state
+ * of encoding enc with these options (host only: no device work, no state).
+ * The planner groups gates into blocks (Sec. 5.2 proposes such fusion); a
+ * gate may move ahead of earlier gates it commutes with (they share no
+ * qubit, or both are diagonal).  order[0..k-1] receives the input index of
+ * each non-identity gate in the order applied; block_len[0..*n_blocks-1]
+ * the number of gates of each consecutive block of that order, and
+ * block_fused[b] (may be NULL) 1 for a fused tile pass, 0 for a single-gate
+ * kernel.  order, block_len and block_fused need room for count entries.
+ * For JQ_COMPACT in PER_BLOCK mode each block is decoded and encoded once.
+ * Validation and errors as jq_apply_circuit. */
+int jq_plan_schedule(int n_qubits, int enc, const jq_gate *gates, size_t count, const jq_exec_opts *opts,
+                     int32_t *order, int32_t *block_len, int32_t *block_fused, size_t *n_blocks);
 
 /* ---- reductions (FP64 whatever the encoding) ------------------------ */
 

@@ -24,8 +24,9 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 # the fused pass dispatches on wave-uniform op codes, so its branches need no
 # structurisation (which would otherwise merge the whole register tile
 # through chains of copy blocks)
-PER_FILE = {"kernels_compact.hip": ["-ffp-contract=off"],
-            "kernels_sv.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
+_UNIFORM = ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]
+PER_FILE = {"kernels_compact.hip": ["-ffp-contract=off"] + _UNIFORM,
+            "kernels_sv.hip": _UNIFORM}
 
 
 def _sources():

@@ -127,6 +127,7 @@ struct Step {
     size_t first_fop = 0;
     int k_reg = 0;          // register bits of the fused kernel
     size_t n_gates = 0;     // source gates covered
+    std::vector<int> gates; // their indices in the op list, in the order applied
 };
 
 struct PlanConfig {
@@ -181,8 +182,13 @@ struct CompactBufs {
 };
 void cp_init(const CompactBufs& b, int n, int mode, uint64_t basis, hipStream_t st);
 void cp_apply_op(const CompactBufs& b, int n, const GateOp& op, hipStream_t st);
-void cp_apply_block(const CompactBufs& b, int n, const std::vector<GateOp>& ops, const FPass& pass,
-                    int k_reg, bool keeps_modulus, hipStream_t st);
+// lane bits of the compact fused pass fixed to index bits 0..F-1 (each
+// code plane is read in runs of 2^F bytes)
+constexpr int kCpFixedLaneBits = 6;
+// one fused pass quantised once: decode, the pass's ops in FP64, range
+// (unless every gate of the block keeps all moduli), encode
+void cp_apply_block(const CompactBufs& b, int n, const FPass& pass, int k_reg, int fixed_lane_bits,
+                    bool keeps_modulus, hipStream_t st);
 void cp_probabilities(const CompactBufs& b, int n, const int* qubits, int nq, double* out_dev,
                       double* partial_dev, size_t partial_cap, hipStream_t st);
 void cp_expectations(const CompactBufs& b, int n, double* out_dev, double* partial_dev, size_t cap,

@@ -22,7 +22,7 @@
 // This file is compiled with -ffp-contract=off: each product and sum
 // rounds on its own, in the order written, so the codes do not depend on
 // fused multiply-adds.
-#include "device_common.hpp"
+#include "fused_ops.hpp"
 
 namespace jq {
 
@@ -407,6 +407,72 @@ __global__ __launch_bounds__(kBlock) void k_cp_dense1_w(int8_t* __restrict__ b0,
     if (!apply) range_flush(lo, hi, acc);
 }
 
+// ------------------------------------------------- fused block pass --
+//
+// Per-block quantisation: the gates of one fused pass run between a single
+// decode and a single encode.  A wavefront takes a tile of 2^(6+K)
+// amplitudes (lane bits 0..F-1 are index bits 0..F-1, so each plane is read
+// in runs of 2^F bytes), decodes it into FP64 registers with the current
+// range and applies the pass's ops as the state-vector pass does.  Range
+// mode then reduces min/max of the new moduli; apply mode encodes with the
+// resolved range and stores both codes.  Waves loop over tiles so that the
+// range reduction issues one atomic pair per wave.
+template <int K, int F, int APPLY>
+__global__ __launch_bounds__(kBlock) void k_cp_fused(int8_t* __restrict__ b0, int8_t* __restrict__ b1, FPass P,
+                                                      const FOp* __restrict__ ops, uint64_t ntiles,
+                                                      const double* __restrict__ rng_old,
+                                                      const double* __restrict__ rng_new,
+                                                      unsigned long long* __restrict__ acc) {
+    constexpr int S = 1 << K;
+    const int lane = threadIdx.x & 63;
+    const uint64_t wpb = blockDim.x >> 6;
+    const uint64_t wave0 = (uint64_t)blockIdx.x * wpb + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * wpb;
+    uint64_t lane_off = (uint64_t)(lane & ((1 << F) - 1));
+#pragma unroll
+    for (int b = F; b < 6; ++b) lane_off |= (uint64_t)((lane >> b) & 1) << P.lane_q[b];
+    uint64_t stride[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) stride[j] = 1ull << P.reg_q[j];
+    const Range ro{rng_old[0], rng_old[1]};
+    Range rn = ro;
+    if (APPLY) rn = Range{rng_new[0], rng_new[1]};
+    double lo = 2.0, hi = 0.0;
+    for (uint64_t w = wave0; w < ntiles; w += nwaves) {
+        const uint64_t base = tile_base(P, w, lane_off);
+        Cx<double> a[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            uint64_t off = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (s & (1 << j)) off += stride[j];
+            a[s] = decode(b0[base + off], b1[base + off], ro);
+        }
+        run_ops<double, K>(a, ops, P.n_ops, base, lane);
+        // recompute the store addresses instead of keeping 2^K of them live
+        uint64_t sbase = base;
+        asm volatile("" : "+v"(sbase));
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            uint64_t off = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (s & (1 << j)) off += stride[j];
+            JQ_SLOT_FENCE();
+            const double m = modulus(a[s]);
+            if (!APPLY) {
+                range_update(m, lo, hi);
+            } else {
+                const int c0 = encode_mod(m, rn);
+                b0[sbase + off] = (int8_t)c0;
+                b1[sbase + off] = (int8_t)(c0 == -128 ? 0 : encode_phase(a[s]));
+            }
+        }
+    }
+    if (!APPLY) range_flush(lo, hi, acc);
+}
+
 // ------------------------------------------------------------ launchers --
 
 namespace {
@@ -577,8 +643,45 @@ void cp_apply_op(const CompactBufs& b, int n, const GateOp& op, hipStream_t st) 
     JQ_HIP(hipMemcpyAsync(b.range, b.range_next, 2 * sizeof(double), hipMemcpyDeviceToDevice, st));
 }
 
-void cp_apply_block(const CompactBufs&, int, const std::vector<GateOp>&, const FPass&, int, bool, hipStream_t) {
-    fail(JQ_EUNSUPPORTED, "compact per-block quantisation is not built");
+namespace {
+
+template <int K, int F>
+void launch_cp_fused(const CompactBufs& b, int n, const FPass& pass, bool keeps, hipStream_t st) {
+    const uint64_t dim = 1ull << n;
+    const uint64_t ntiles = 1ull << (n - 6 - K);
+    const unsigned wpb = (unsigned)(ntiles < 4 ? ntiles : 4);
+    const uint64_t blocks_needed = ntiles / wpb;
+    // enough waves to fill the chip several times over; each loops over tiles
+    const unsigned blocks = (unsigned)(blocks_needed < 4096 ? blocks_needed : 4096);
+    int8_t* b0 = b.codes;
+    int8_t* b1 = b.codes + dim;
+    unsigned long long* acc = (unsigned long long*)b.acc;
+    if (!keeps) {
+        hipLaunchKernelGGL((k_cp_fused<K, F, 0>), dim3(blocks), dim3(64 * wpb), 0, st, b0, b1, pass, pass.ops, ntiles,
+                           (const double*)b.range, (const double*)b.range_next, acc);
+        JQ_HIP(hipGetLastError());
+    }
+    // keeps: acc still holds its reset value, so resolve copies the old range
+    hipLaunchKernelGGL(k_cp_resolve, dim3(1), dim3(64), 0, st, acc, (const double*)b.range, b.range_next);
+    hipLaunchKernelGGL((k_cp_fused<K, F, 1>), dim3(blocks), dim3(64 * wpb), 0, st, b0, b1, pass, pass.ops, ntiles,
+                       (const double*)b.range, (const double*)b.range_next, acc);
+    JQ_HIP(hipGetLastError());
+    JQ_HIP(hipMemcpyAsync(b.range, b.range_next, 2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+}
+
+}  // namespace
+
+void cp_apply_block(const CompactBufs& b, int n, const FPass& pass, int k_reg, int fixed_lane_bits, bool keeps,
+                    hipStream_t st) {
+    ensure_lut();
+    if (n < 6 + k_reg) fail(JQ_EINVAL, "compact fused pass: state smaller than a tile");
+    if (fixed_lane_bits != kCpFixedLaneBits) fail(JQ_EINVAL, "compact fused pass: unsupported lane layout");
+    switch (k_reg) {
+        case 2: launch_cp_fused<2, kCpFixedLaneBits>(b, n, pass, keeps, st); break;
+        case 3: launch_cp_fused<3, kCpFixedLaneBits>(b, n, pass, keeps, st); break;
+        case 4: launch_cp_fused<4, kCpFixedLaneBits>(b, n, pass, keeps, st); break;
+        default: fail(JQ_EINVAL, "compact fused pass: register bits must be 2..4");
+    }
 }
 
 void cp_probabilities(const CompactBufs& b, int n, const int* qubits, int nq, double* out, double* partial, size_t cap,

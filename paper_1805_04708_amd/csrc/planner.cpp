@@ -289,6 +289,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
             Step s;
             s.op = op;
             s.n_gates = 1;
+            s.gates.push_back((int)plan.steps.size());
             plan.steps.push_back(s);
         }
         return plan;
@@ -328,6 +329,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
             Step s;
             s.op = ops[remaining[0]];
             s.n_gates = 1;
+            s.gates.push_back(remaining[0]);
             plan.steps.push_back(s);
             remaining.erase(remaining.begin());
             continue;
@@ -346,6 +348,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
                 Step s;
                 s.op = ops[i];
                 s.n_gates = 1;
+                s.gates.push_back(i);
                 plan.steps.push_back(s);
             }
             continue;
@@ -395,6 +398,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
         }
         p.n_ops = n_ops;
         s.n_gates = pb.taken.size();
+        s.gates = pb.taken;
         plan.steps.push_back(s);
     }
     return plan;

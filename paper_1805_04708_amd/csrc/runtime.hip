@@ -56,9 +56,11 @@ int guarded(F&& f) {
 
 // ------------------------------------------------------ kernel timing --
 
-enum KClass { K_DENSE1, K_DENSE2, K_DIAG, K_PERMX, K_FUSED, K_CP_GATE, K_CP_PERM, K_CP_PHASE, K_REDUCE, K_NCLASS };
-const char* kClassName[K_NCLASS] = {"dense1", "dense2", "diag", "permx", "fused",
-                                    "compact_gate", "compact_perm", "compact_phase", "reduce"};
+enum KClass {
+    K_DENSE1, K_DENSE2, K_DIAG, K_PERMX, K_FUSED, K_CP_GATE, K_CP_PERM, K_CP_PHASE, K_REDUCE, K_CP_FUSED, K_NCLASS
+};
+const char* kClassName[K_NCLASS] = {"dense1", "dense2", "diag", "permx", "fused", "compact_gate",
+                                    "compact_perm", "compact_phase", "reduce", "compact_fused"};
 
 struct Timed {
     jq_state* s;
@@ -168,19 +170,25 @@ void run_single(jq_state* s, const GateOp& op) {
     else sv_apply_op(s->enc, s->buf, s->n, op, s->stream);
 }
 
-PlanConfig plan_config(const jq_state* s, const jq_exec_opts* opts) {
+// Kernel layout per encoding: fixed lane bits F (128-byte lines for the
+// state vector; 64-byte runs of each code plane) and register bits K.
+// Compact states fuse only in per-block quantisation mode.
+PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
     PlanConfig c;
-    c.n = s->n;
-    c.fixed_lane_bits = s->enc == JQ_C64 ? 4 : 3;
-    c.k_reg = s->enc == JQ_C64 ? 5 : 4;
+    c.n = n;
+    const bool compact = enc == JQ_COMPACT;
+    c.fixed_lane_bits = compact ? kCpFixedLaneBits : enc == JQ_C64 ? 4 : 3;
+    c.k_reg = compact ? 4 : enc == JQ_C64 ? 5 : 4;
+    const int k_max = compact ? 4 : enc == JQ_C64 ? 6 : 5;
     c.max_ops = 48;
-    c.fuse = s->enc != JQ_COMPACT;
+    c.fuse = !compact;
     if (opts) {
+        if (opts->compact_mode != JQ_COMPACT_PER_GATE && opts->compact_mode != JQ_COMPACT_PER_BLOCK)
+            fail(JQ_EINVAL, "jq_exec_opts: bad compact_mode");
+        if (compact && opts->compact_mode == JQ_COMPACT_PER_BLOCK) c.fuse = true;
         if (opts->fusion == 1) c.fuse = false;
-        else if (opts->fusion >= 2) c.k_reg = std::min(opts->fusion, s->enc == JQ_C64 ? 6 : 5);
+        else if (opts->fusion >= 2) c.k_reg = std::min(opts->fusion, k_max);
         if (opts->max_ops > 0) c.max_ops = std::min(opts->max_ops, 256);
-        if (s->enc == JQ_COMPACT && opts->compact_mode == JQ_COMPACT_PER_BLOCK)
-            fail(JQ_EUNSUPPORTED, "compact per-block quantisation is not built");
     }
     while (c.fuse && c.k_reg > 2 && c.n < 6 + c.k_reg) c.k_reg--;
     return c;
@@ -221,12 +229,11 @@ void upload_fops(jq_state* s, const std::vector<FOp>& fops) {
     JQ_HIP(hipEventRecord(s->plan_ev, s->stream));
 }
 
-void apply_ops(jq_state* s, const std::vector<GateOp>& ops, const jq_exec_opts* opts) {
-    const PlanConfig cfg = plan_config(s, opts);
+void apply_ops(jq_state* s, const std::vector<GateOp>& ops, const PlanConfig& cfg) {
     Plan plan = make_plan(ops, cfg);
     upload_fops(s, plan.fops);
     const FOp* dev = (const FOp*)s->plan_dev;
-    const double full = 2.0 * std::ldexp(1.0, s->n) * bytes_per_amp(s->enc);
+    const double sweep = std::ldexp(1.0, s->n) * bytes_per_amp(s->enc);
     for (auto& step : plan.steps) {
         if (!step.fused) {
             run_single(s, step.op);
@@ -234,7 +241,14 @@ void apply_ops(jq_state* s, const std::vector<GateOp>& ops, const jq_exec_opts* 
         }
         FPass p = step.pass;
         p.ops = dev + step.first_fop;
-        Timed t(s, K_FUSED, full);
+        if (s->enc == JQ_COMPACT) {
+            bool keeps = true;
+            for (int g : step.gates) keeps = keeps && ops[g].keeps_modulus;
+            Timed t(s, K_CP_FUSED, (keeps ? 2.0 : 3.0) * sweep);
+            cp_apply_block(compact_bufs(s), s->n, p, step.k_reg, cfg.fixed_lane_bits, keeps, s->stream);
+            continue;
+        }
+        Timed t(s, K_FUSED, 2.0 * sweep);
         sv_apply_fused(s->enc, s->buf, s->n, p, step.k_reg, cfg.fixed_lane_bits, s->stream);
     }
 }
@@ -327,12 +341,7 @@ jq_state* state_create(int n, int enc, hipStream_t stream, bool async_alloc) {
 }
 
 void state_apply(jq_state* s, const std::vector<GateOp>& ops, const jq_exec_opts* opts) {
-    (void)plan_config(s, opts);
-    if (s->enc == JQ_COMPACT) {
-        for (const auto& op : ops) run_single(s, op);
-        return;
-    }
-    apply_ops(s, ops, opts);
+    apply_ops(s, ops, plan_config(s->n, s->enc, opts));
 }
 
 void state_norm_async(jq_state* s, double* pinned_out) {
@@ -515,12 +524,37 @@ int jq_apply_circuit(jq_state* s, const jq_gate* gates, size_t count, const jq_e
                 fail(e.code, "gate " + std::to_string(i) + ": " + e.what());
             }
         }
-        (void)plan_config(s, opts);  // validates options before any work
-        if (s->enc == JQ_COMPACT) {
-            for (const auto& op : ops) run_single(s, op);
-            return;
+        apply_ops(s, ops, plan_config(s->n, s->enc, opts));  // options validated before any work
+    });
+}
+
+int jq_plan_schedule(int n_qubits, int enc, const jq_gate* gates, size_t count, const jq_exec_opts* opts,
+                     int32_t* order, int32_t* block_len, int32_t* block_fused, size_t* n_blocks) {
+    return guarded([&] {
+        if (n_qubits < 1 || n_qubits > JQ_MAX_QUBITS) fail(JQ_EINVAL, "jq_plan_schedule: N must be in [1, 63]");
+        if (enc != JQ_C128 && enc != JQ_C64 && enc != JQ_COMPACT) fail(JQ_EINVAL, "jq_plan_schedule: bad encoding");
+        if (!n_blocks) fail(JQ_EINVAL, "jq_plan_schedule: null n_blocks");
+        if (count && (!gates || !order || !block_len)) fail(JQ_EINVAL, "jq_plan_schedule: null array");
+        std::vector<GateOp> ops;
+        std::vector<int32_t> src;
+        for (size_t i = 0; i < count; ++i) {
+            if (gates[i].nq == 0) continue;  // identity
+            try {
+                ops.push_back(canonicalize(gates[i], n_qubits));
+            } catch (const Error& e) {
+                fail(e.code, "gate " + std::to_string(i) + ": " + e.what());
+            }
+            src.push_back((int32_t)i);
         }
-        apply_ops(s, ops, opts);
+        const Plan plan = make_plan(ops, plan_config(n_qubits, enc, opts));
+        size_t k = 0, b = 0;
+        for (const auto& step : plan.steps) {
+            for (int g : step.gates) order[k++] = src[g];
+            block_len[b] = (int32_t)step.gates.size();
+            if (block_fused) block_fused[b] = step.fused ? 1 : 0;
+            ++b;
+        }
+        *n_blocks = b;
     });
 }
 

@@ -83,6 +83,10 @@ SIGNATURES = {
     "jq_gate_named": (ctypes.c_int, [ctypes.c_char_p, _IP, ctypes.c_int, _DP, ctypes.c_int, ctypes.POINTER(Gate)]),
     "jq_apply_gate": (ctypes.c_int, [_VP, ctypes.c_int, _IP, ctypes.c_int, _IP, ctypes.c_int, _DP]),
     "jq_apply_circuit": (ctypes.c_int, [_VP, ctypes.POINTER(Gate), ctypes.c_size_t, ctypes.POINTER(ExecOpts)]),
+    "jq_plan_schedule": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Gate), ctypes.c_size_t,
+                                        ctypes.POINTER(ExecOpts), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_size_t)]),
     "jq_norm": (ctypes.c_int, [_VP, _DP]),
     "jq_probabilities": (ctypes.c_int, [_VP, _IP, ctypes.c_int, _DP]),
     "jq_expectations": (ctypes.c_int, [_VP, _DP, _DP, _DP]),
@@ -170,6 +174,24 @@ def exec_opts(fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0):
     o = ExecOpts()
     o.fusion, o.compact_mode, o.max_ops = fusion, compact_mode, max_ops
     return o
+
+
+def plan_schedule(n, enc, circuit, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0):
+    """Host-only schedule of jq_apply_circuit: (order, block_len, block_fused),
+    order being input gate indices in the order applied, split into
+    consecutive blocks of block_len gates (fused tile pass or single gate)."""
+    arr, cnt = circuit if isinstance(circuit, tuple) else gates(circuit)
+    opts = exec_opts(fusion, compact_mode, max_ops)
+    m = max(1, cnt)
+    order = np.zeros(m, dtype=np.int32)
+    blen = np.zeros(m, dtype=np.int32)
+    bfused = np.zeros(m, dtype=np.int32)
+    nb = ctypes.c_size_t()
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    check(lib().jq_plan_schedule(n, ENCODINGS.get(enc, enc), arr, cnt, ctypes.byref(opts), order.ctypes.data_as(i32),
+                                 blen.ctypes.data_as(i32), bfused.ctypes.data_as(i32), ctypes.byref(nb)))
+    k = int(blen[:nb.value].sum())
+    return order[:k].copy(), blen[:nb.value].copy(), bfused[:nb.value].astype(bool)
 
 
 # -------------------------------------------------------------- state --

@@ -1,0 +1,126 @@
+"""The planner's schedule (jq_plan_schedule, host only): which gates run
+together in one tile pass and in which order.  These checks need no GPU:
+the order must be a permutation of the circuit that the oracle maps to the
+same state (gates only move past gates they commute with), every fused
+block must fit one tile, and the options select the documented modes."""
+import numpy as np
+import pytest
+
+from oracle import core as O
+from paper_1805_04708_amd import jq
+from paper_1805_04708_amd import workloads as W
+
+# tile shape per encoding: fixed lane bits F, default register bits K
+LAYOUT = {"c128": (3, 4), "c64": (4, 5), "compact": (6, 4)}
+PER_BLOCK = jq.JQ_COMPACT_PER_BLOCK
+
+
+def schedule(n, enc, circ, **kw):
+    order, blen, fused = jq.plan_schedule(n, enc, circ, **kw)
+    return list(order), list(blen), list(fused)
+
+
+def non_identity(circ):
+    return [i for i, g in enumerate(circ) if g[0] != "I"]
+
+
+def circuits(n):
+    return [W.random_circuit(n, 200, seed=n), W.layered_u2_cz(n, 3, seed=n),
+            W.rz_cnot_chain(n, 3, seed=n), W.qft(n)]
+
+
+def targets_of(g):
+    # qubits a gate changes the value of (diagonal gates change none)
+    name, q = g[0], list(g[1])
+    if name in ("Z", "S", "S+", "T", "T+", "U1", "R", "RZ", "U", "CZ", "CP", "I"):
+        return []
+    if name == "CNOT":
+        return [q[1]]
+    if name == "TOFFOLI":
+        return [q[2]]
+    return q
+
+
+@pytest.mark.parametrize("n", [8, 12, 16])
+@pytest.mark.parametrize("enc,kw", [("c128", {}), ("c64", {}), ("c128", {"fusion": 2}),
+                                    ("c128", {"fusion": 5}), ("compact", {"compact_mode": PER_BLOCK})])
+def test_schedule_is_a_commuting_reordering(n, enc, kw):
+    for circ in circuits(n):
+        order, blen, fused = schedule(n, enc, circ, **kw)
+        assert sorted(order) == non_identity(circ)
+        assert sum(blen) == len(order) and all(b >= 1 for b in blen)
+        assert all(f or b == 1 for b, f in zip(blen, fused))
+        # the reordered circuit is the same unitary: same state from a
+        # random start, to rounding
+        rng = np.random.default_rng(n)
+        psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+        psi /= np.linalg.norm(psi)
+        a = O.run(psi.copy(), n, circ)
+        b = O.run(psi.copy(), n, [circ[i] for i in order])
+        assert O.rel_l2(b, a) < 1e-13
+
+
+@pytest.mark.parametrize("enc,kw", [("c128", {}), ("c64", {}), ("c128", {"fusion": 3}),
+                                    ("compact", {"compact_mode": PER_BLOCK})])
+def test_fused_blocks_fit_one_tile(enc, kw):
+    n = 20
+    F, K = LAYOUT[enc]
+    if "fusion" in kw:
+        K = kw["fusion"]
+    for circ in circuits(n):
+        order, blen, fused = schedule(n, enc, circ, **kw)
+        pos = 0
+        n_fused = 0
+        for b, f in zip(blen, fused):
+            blk = [circ[i] for i in order[pos:pos + b]]
+            pos += b
+            if not f:
+                continue
+            n_fused += 1
+            free = {q for g in blk for q in targets_of(g)} - set(range(F))
+            assert len(free) <= (6 - F) + K, (enc, sorted(free))
+            assert all(len(g[1]) - (1 if g[0] == "CNOT" else 2 if g[0] == "TOFFOLI" else 0) <= 1 or
+                       not targets_of(g) for g in blk), "two-qubit dense gates run unfused"
+        assert n_fused > 0
+
+
+def test_unfused_modes_keep_the_input_order():
+    n = 12
+    circ = W.random_circuit(n, 100, seed=4) + [("I", (3,), ())]
+    for enc, kw in [("c128", {"fusion": 1}), ("c64", {"fusion": 1}), ("compact", {}),
+                    ("compact", {"compact_mode": PER_BLOCK, "fusion": 1})]:
+        order, blen, fused = schedule(n, enc, circ, **kw)
+        assert order == non_identity(circ)
+        assert blen == [1] * len(order) and not any(fused)
+
+
+def test_small_states_fall_back_to_single_gates():
+    # a tile needs 6 + K >= 8 index bits
+    for n in (1, 4, 7):
+        circ = W.random_circuit(n, 40, seed=n) if n > 1 else [("H", (0,), ()), ("T", (0,), ())]
+        for enc, kw in [("c128", {}), ("compact", {"compact_mode": PER_BLOCK})]:
+            order, blen, fused = schedule(n, enc, circ, **kw)
+            assert not any(fused) and order == non_identity(circ)
+
+
+def test_keeps_modulus_blocks_are_recognisable():
+    # a layer of RZ and the CNOT chain: every block keeps all moduli, so a
+    # per-block compact run keeps the range (checked on the GPU); here the
+    # blocks must exist and cover the circuit
+    n = 14
+    circ = W.rz_cnot_chain(n, 2, seed=1)
+    order, blen, fused = schedule(n, "compact", circ, compact_mode=PER_BLOCK)
+    assert any(fused) and sum(blen) == len(circ)
+
+
+def test_schedule_errors():
+    circ = [("H", (0,), ())]
+    with pytest.raises(jq.JqError):
+        jq.plan_schedule(0, "c128", circ)
+    with pytest.raises(jq.JqError):
+        jq.plan_schedule(4, 7, circ)
+    with pytest.raises(jq.JqError):
+        jq.plan_schedule(4, "compact", circ, compact_mode=5)
+    with pytest.raises(jq.JqError) as e:
+        jq.plan_schedule(2, "c128", [("H", (0,), ()), ("H", (2,), ())])
+    assert e.value.code == jq.JQ_EINVAL and "gate 1" in str(e.value)
