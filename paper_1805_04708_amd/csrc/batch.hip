@@ -117,23 +117,24 @@ __device__ __forceinline__ void block_diag(Cx<R> (&a)[1 << KB], const BOp* op, u
     }
 }
 
-template <typename R, int KB>
-__device__ __forceinline__ void block_dense2(Cx<R> (&a)[1 << KB], const BOp* op, uint32_t base, const int (&q)[3]) {
-    if constexpr (KB >= 2) {
-        const int jh = op->slot, jl = op->slot2;
+// Two-qubit dense op on register slots JH (matrix MSB) and JL, both known at
+// compile time so that the register tile is never indexed at run time.
+template <typename R, int KB, int JH, int JL>
+__device__ __forceinline__ void block_dense2_t(Cx<R> (&a)[1 << KB], const BOp* op, uint32_t base,
+                                               const int (&q)[3]) {
+    if constexpr (KB >= 2 && JH < KB && JL < KB && JH != JL) {
         const uint32_t cm = op->cmask;
 #pragma unroll
         for (int s = 0; s < (1 << KB); ++s) {
-            if (((s >> jh) & 1) || ((s >> jl) & 1)) continue;
+            if (((s >> JH) & 1) || ((s >> JL) & 1)) continue;
             uint32_t idx = base;
 #pragma unroll
             for (int i = 0; i < KB; ++i)
                 if ((s >> i) & 1) idx |= 1u << q[i];
             const bool ok = (idx & cm) == cm;
-            const int sl[4] = {s, s | (1 << jl), s | (1 << jh), s | (1 << jh) | (1 << jl)};
-            Cx<R> x[4], y[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) x[c] = a[sl[c]];
+            constexpr int h = 1 << JH, l = 1 << JL;
+            Cx<R> x[4] = {a[s], a[s | l], a[s | h], a[s | h | l]};
+            Cx<R> y[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 Cx<R> acc = cmulf(Cx<R>{(R)op->m[8 * r], (R)op->m[8 * r + 1]}, x[0]);
@@ -142,9 +143,25 @@ __device__ __forceinline__ void block_dense2(Cx<R> (&a)[1 << KB], const BOp* op,
                     acc = cadd(acc, cmulf(Cx<R>{(R)op->m[8 * r + 2 * c], (R)op->m[8 * r + 2 * c + 1]}, x[c]));
                 y[r] = acc;
             }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) a[sl[c]] = csel(ok, y[c], x[c]);
+            a[s] = csel(ok, y[0], x[0]);
+            a[s | l] = csel(ok, y[1], x[1]);
+            a[s | h] = csel(ok, y[2], x[2]);
+            a[s | h | l] = csel(ok, y[3], x[3]);
         }
+    }
+}
+
+template <typename R, int KB>
+__device__ __forceinline__ void block_dense2(Cx<R> (&a)[1 << KB], const BOp* op, uint32_t base, const int (&q)[3]) {
+    // one empty asm statement per case, as in run_block's slot switch
+    switch (op->slot * 4 + op->slot2) {
+        case 1: block_dense2_t<R, KB, 0, 1>(a, op, base, q); asm volatile("; batch pair 01"); break;
+        case 2: block_dense2_t<R, KB, 0, 2>(a, op, base, q); asm volatile("; batch pair 02"); break;
+        case 4: block_dense2_t<R, KB, 1, 0>(a, op, base, q); asm volatile("; batch pair 10"); break;
+        case 6: block_dense2_t<R, KB, 1, 2>(a, op, base, q); asm volatile("; batch pair 12"); break;
+        case 8: block_dense2_t<R, KB, 2, 0>(a, op, base, q); asm volatile("; batch pair 20"); break;
+        case 9: block_dense2_t<R, KB, 2, 1>(a, op, base, q); asm volatile("; batch pair 21"); break;
+        default: break;
     }
 }
 
@@ -184,12 +201,16 @@ __device__ void run_block(typename Vec<R>::T* S, int n, const BBlock& blk, const
                 case B_DENSE:
                 case B_PERM: {
                     const int j = op->slot;
+// Each case ends in its own empty asm statement so that the compiler cannot
+// merge the cases into one body with a run-time slot (which would move the
+// register tile to scratch memory).
 #define JQ_BCASE(J)                                                                        \
     case J:                                                                                \
         if constexpr (J < KB) {                                                            \
             if (op->kind == B_DENSE) block_dense<R, KB>(a, J, op, base, q);                \
             else block_perm<R, KB>(a, J, op, base, q);                                     \
         }                                                                                  \
+        asm volatile("; batch slot " #J);                                                  \
         break;
                     switch (j) {
                         JQ_BCASE(0)

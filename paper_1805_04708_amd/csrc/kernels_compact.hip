@@ -88,6 +88,133 @@ __device__ __forceinline__ void range_flush(double lo, double hi, unsigned long 
     }
 }
 
+// ------------------------------------------------ fast codec paths --
+//
+// The codes are defined by the FP64 formulas above.  The kernels below take
+// them through cheaper routes that give the same code:
+// * decode reads r(b0) from a per-block LDS table holding the decode
+//   formula's value for each of the 256 codes, and cos/sin of the phase
+//   code from LDS;
+// * the range is reduced over x = re^2 + im^2: the correctly rounded square
+//   root is monotone, so min/max of sqrt(x) are sqrt of min/max of x, and
+//   sqrt(x) < 1 - kOneTol holds exactly when x < c_x_one, the least double
+//   whose square root reaches 1 - kOneTol (found on the host);
+// * an estimate of the code's real-valued argument (the modulus ratio from
+//   a refined hardware reciprocal square root, the phase from an FP32
+//   atan2 of the power-of-two-scaled amplitude) decides the code when it
+//   lies farther from a rounding boundary than a bound on the estimate's
+//   error; otherwise the FP64 formula runs.
+
+__constant__ double c_x_one;
+
+struct DecodeTab {
+    double r[256], c[256], s[256];
+};
+
+// every thread of the block calls this (it ends with a barrier)
+__device__ __forceinline__ void decode_tab_fill(DecodeTab& T, Range g) {
+    for (int k = (int)threadIdx.x; k < 256; k += (int)blockDim.x) {
+        const int c0 = k - 128;
+        T.r[k] = c0 == -128 ? 0.0 : c0 == 127 ? 1.0 : ((double)(c0 + 127) * (g.r1 - g.r0)) / 253.0 + g.r0;
+        T.c[k] = c_cos[k];
+        T.s[k] = c_sin[k];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ Cx<double> decode_tab(const DecodeTab& T, int c0, int c1) {
+    const double r = T.r[c0 + 128];
+    return {r * T.c[c1 + 128], r * T.s[c1 + 128]};
+}
+
+__device__ __forceinline__ double modulus2(Cx<double> z) { return z.re * z.re + z.im * z.im; }
+
+__device__ __forceinline__ void range_update_x(double x, double& lo, double& hi) {
+    if (x > 0.0 && x < c_x_one) {
+        lo = x < lo ? x : lo;
+        hi = x > hi ? x : hi;
+    }
+}
+
+__device__ __forceinline__ void range_flush_x(double lo, double hi, unsigned long long* acc) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const double l2 = __shfl_xor(lo, off, 64), h2 = __shfl_xor(hi, off, 64);
+        lo = l2 < lo ? l2 : lo;
+        hi = h2 > hi ? h2 : hi;
+    }
+    if ((threadIdx.x & 63) == 0 && hi > 0.0) {
+        atomicMin(&acc[0], dbits(sqrt(lo)));
+        atomicMax(&acc[1], dbits(sqrt(hi)));
+    }
+}
+
+struct EncParams {
+    double r0, r1;
+    double inv;  // 253 / (r1 - r0)
+};
+
+__device__ __forceinline__ EncParams enc_params(Range g) {
+    return {g.r0, g.r1, g.r1 > g.r0 ? 253.0 / (g.r1 - g.r0) : 0.0};
+}
+
+// The FP64 formulas out of line: they run only for the few amplitudes the
+// estimates cannot decide, and inlining them into every register slot of
+// an unrolled tile would multiply the kernel's code size.
+__device__ __attribute__((noinline)) int encode_mod_slow(double x, double r0, double r1) {
+    return encode_mod(sqrt(x), Range{r0, r1});
+}
+
+__device__ __attribute__((noinline)) int encode_phase_slow(double re, double im) {
+    return encode_phase(Cx<double>{re, im});
+}
+
+// b0 of an amplitude with x = re^2 + im^2: encode_mod(sqrt(x)).
+__device__ __forceinline__ int encode_mod_x(double x, const EncParams& p) {
+    if (x == 0.0) return -128;
+    if (x >= c_x_one) return 127;
+    if (p.r1 == p.r0) return -127;
+    if (x >= 0x1p-900) {
+        // v_rsq_f64 (relative error far below 2^-20) and one Goldschmidt
+        // step: a within 2^-40 relative of sqrt(x)
+        const double y = __builtin_amdgcn_rsq(x);
+        double a = x * y;
+        const double h = 0.5 * y;
+        a = fma(a, fma(-h, a, 0.5), a);
+        // the FP64 formula's argument differs from q by less than
+        // inv * a * 2^-43 + 2^-42
+        const double q = (a - p.r0) * p.inv;
+        const double f = q - floor(q);
+        if (fabs(f - 0.5) > p.inv * a * 0x1p-36 + 1e-9) {
+            double v = -127.0 + rint(q);
+            v = v < -127.0 ? -127.0 : v;
+            v = v > 126.0 ? 126.0 : v;
+            return (int)v;
+        }
+    }
+    return encode_mod_slow(x, p.r0, p.r1);
+}
+
+// b1 of a non-zero amplitude: encode_phase(z).
+__device__ __forceinline__ int encode_phase_fast(Cx<double> z) {
+    const double m = fmax(fabs(z.re), fabs(z.im));
+    int e = 0;
+    (void)frexp(m, &e);
+    const float xf = (float)ldexp(z.re, -e), yf = (float)ldexp(z.im, -e);
+    // error of t: scaling is exact, the FP32 conversions and atan2f add a
+    // few 2^-24 of the angle, the product a few ulps of 128: below 1e-4
+    // code units in all
+    const float t = atan2f(yf, xf) * (float)(128.0 / kPiD);
+    const float fl = floorf(t);
+    const float f = t - fl;
+    if (fabsf(f - 0.5f) > 1e-3f) {
+        int c = (int)fl + (f > 0.5f ? 1 : 0);
+        if (c >= 128) c -= 256;
+        if (c < -128) c += 256;
+        return c;
+    }
+    return encode_phase_slow(z.re, z.im);
+}
+
 struct CpGate {
     int32_t kind;     // OP_DENSE1, OP_DENSE2, OP_DIAG
     int32_t nsel;
@@ -110,6 +237,9 @@ __global__ __launch_bounds__(kBlock) void k_cp_gate(int8_t* __restrict__ b0, int
     const Range ro{rng_old[0], rng_old[1]};
     Range rn = ro;
     if (apply) rn = Range{rng_new[0], rng_new[1]};
+    const EncParams ep = enc_params(rn);
+    __shared__ DecodeTab tab;
+    decode_tab_fill(tab, ro);
     double lo = 2.0, hi = 0.0;
     for (uint64_t gi = (uint64_t)blockIdx.x * kBlock + threadIdx.x; gi < ngroups;
          gi += (uint64_t)gridDim.x * kBlock) {
@@ -128,13 +258,13 @@ __global__ __launch_bounds__(kBlock) void k_cp_gate(int8_t* __restrict__ b0, int
         }
         Cx<double> z[A], w[A];
 #pragma unroll
-        for (int c = 0; c < A; ++c) z[c] = decode(b0[idx[c]], b1[idx[c]], ro);
+        for (int c = 0; c < A; ++c) z[c] = decode_tab(tab, b0[idx[c]], b1[idx[c]]);
         const bool on = (i & g.cmask) == g.cmask;
         if constexpr (KIND == OP_DIAG) {
             int sel = 0;
             if (g.nsel >= 1) sel = (int)((i >> g.t0) & 1);
             if (g.nsel == 2) sel = 2 * sel + (int)((i >> g.t1) & 1);
-            w[0] = on ? cmul(g.m[sel], z[0]) : z[0];
+            w[0] = csel(on, cmul(g.m[sel], z[0]), z[0]);
         } else {
 #pragma unroll
             for (int r = 0; r < A; ++r) {
@@ -142,22 +272,22 @@ __global__ __launch_bounds__(kBlock) void k_cp_gate(int8_t* __restrict__ b0, int
                 Cx<double> s = cmul(g.m[A * r], z[0]);
 #pragma unroll
                 for (int c = 1; c < A; ++c) s = cadd(s, cmul(g.m[A * r + c], z[c]));
-                w[r] = on ? s : z[r];
+                w[r] = csel(on, s, z[r]);
             }
         }
         if (!apply) {
 #pragma unroll
-            for (int c = 0; c < A; ++c) range_update(modulus(w[c]), lo, hi);
+            for (int c = 0; c < A; ++c) range_update_x(modulus2(w[c]), lo, hi);
         } else {
 #pragma unroll
             for (int c = 0; c < A; ++c) {
-                const int c0 = encode_mod(modulus(w[c]), rn);
+                const int c0 = encode_mod_x(modulus2(w[c]), ep);
                 b0[idx[c]] = (int8_t)c0;
-                b1[idx[c]] = (int8_t)(c0 == -128 ? 0 : encode_phase(w[c]));
+                b1[idx[c]] = (int8_t)(c0 == -128 ? 0 : encode_phase_fast(w[c]));
             }
         }
     }
-    if (!apply) range_flush(lo, hi, acc);
+    if (!apply) range_flush_x(lo, hi, acc);
 }
 
 __global__ void k_cp_resolve(unsigned long long* acc, const double* rng_old, double* rng_new) {
@@ -363,48 +493,72 @@ __global__ __launch_bounds__(kBlock) void k_cp_shift_w(const int8_t* __restrict_
     }
 }
 
-// Dense single-qubit gate over all pairs (target bit t, W <= 2^t), range or
-// apply mode as in k_cp_gate.
+// W codes of one plane packed into 32-bit words (byte u of the chunk is
+// bits 8(u%4).. of word u/4), written with one 4- or 16-byte store.
 template <int W>
+struct Pack {
+    uint32_t w[W >= 4 ? W / 4 : 1] = {};
+    __device__ __forceinline__ void set(int u, int code) { w[u >> 2] |= (uint32_t)(uint8_t)code << (8 * (u & 3)); }
+};
+
+template <int W>
+__device__ __forceinline__ void stp(int8_t* p, uint64_t i, const Pack<W>& c) {
+    if constexpr (W == 16) {
+        *reinterpret_cast<uint4*>(p + i) = make_uint4(c.w[0], c.w[1], c.w[2], c.w[3]);
+    } else if constexpr (W == 4) {
+        *reinterpret_cast<uint32_t*>(p + i) = c.w[0];
+    } else {
+        p[i] = (int8_t)(c.w[0] & 0xff);
+    }
+}
+
+// Dense single-qubit gate over all pairs (target bit t, W <= 2^t): range
+// mode (APPLY = 0) reduces the new moduli, apply mode encodes them with the
+// resolved range, as in k_cp_gate.
+template <int W, int APPLY>
 __global__ __launch_bounds__(kBlock) void k_cp_dense1_w(int8_t* __restrict__ b0, int8_t* __restrict__ b1,
                                                          uint64_t nchunks, Ins ins, uint64_t tbit, CpGate g,
                                                          const double* __restrict__ rng_old,
                                                          const double* __restrict__ rng_new,
-                                                         unsigned long long* __restrict__ acc, int apply) {
+                                                         unsigned long long* __restrict__ acc) {
     const Range ro{rng_old[0], rng_old[1]};
     Range rn = ro;
-    if (apply) rn = Range{rng_new[0], rng_new[1]};
+    if (APPLY) rn = Range{rng_new[0], rng_new[1]};
+    const EncParams ep = enc_params(rn);
+    __shared__ DecodeTab tab;
+    decode_tab_fill(tab, ro);
     double lo = 2.0, hi = 0.0;
     for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < nchunks; c += (uint64_t)gridDim.x * kBlock) {
         const uint64_t i = expand(c * W, ins), j = i | tbit;
-        Codes<W> x0 = ldc<W>(b0, i), x1 = ldc<W>(b1, i), y0 = ldc<W>(b0, j), y1 = ldc<W>(b1, j);
+        const Codes<W> x0 = ldc<W>(b0, i), x1 = ldc<W>(b1, i), y0 = ldc<W>(b0, j), y1 = ldc<W>(b1, j);
+        Pack<W> px0, px1, py0, py1;
 #pragma unroll
         for (int u = 0; u < W; ++u) {
-            const Cx<double> z0 = decode(x0.v[u], x1.v[u], ro), z1 = decode(y0.v[u], y1.v[u], ro);
+            const Cx<double> z0 = decode_tab(tab, x0.v[u], x1.v[u]), z1 = decode_tab(tab, y0.v[u], y1.v[u]);
             const bool on = ((i + u) & g.cmask) == g.cmask;
             Cx<double> w0 = cadd(cmul(g.m[0], z0), cmul(g.m[1], z1));
             Cx<double> w1 = cadd(cmul(g.m[2], z0), cmul(g.m[3], z1));
-            w0 = on ? w0 : z0;
-            w1 = on ? w1 : z1;
-            if (!apply) {
-                range_update(modulus(w0), lo, hi);
-                range_update(modulus(w1), lo, hi);
+            w0 = csel(on, w0, z0);
+            w1 = csel(on, w1, z1);
+            if constexpr (!APPLY) {
+                range_update_x(modulus2(w0), lo, hi);
+                range_update_x(modulus2(w1), lo, hi);
             } else {
-                const int c0 = encode_mod(modulus(w0), rn), c1 = encode_mod(modulus(w1), rn);
-                x0.v[u] = (int8_t)c0;
-                x1.v[u] = (int8_t)(c0 == -128 ? 0 : encode_phase(w0));
-                y0.v[u] = (int8_t)c1;
-                y1.v[u] = (int8_t)(c1 == -128 ? 0 : encode_phase(w1));
+                const int c0 = encode_mod_x(modulus2(w0), ep), c1 = encode_mod_x(modulus2(w1), ep);
+                px0.set(u, c0);
+                px1.set(u, c0 == -128 ? 0 : encode_phase_fast(w0));
+                py0.set(u, c1);
+                py1.set(u, c1 == -128 ? 0 : encode_phase_fast(w1));
             }
         }
-        if (apply) {
-            stc<W>(b0, i, x0);
-            stc<W>(b1, i, x1);
-            stc<W>(b0, j, y0);
-            stc<W>(b1, j, y1);
+        if constexpr (APPLY) {
+            stp<W>(b0, i, px0);
+            stp<W>(b1, i, px1);
+            stp<W>(b0, j, py0);
+            stp<W>(b1, j, py1);
         }
     }
-    if (!apply) range_flush(lo, hi, acc);
+    if constexpr (!APPLY) range_flush_x(lo, hi, acc);
 }
 
 // ------------------------------------------------- fused block pass --
@@ -437,6 +591,9 @@ __global__ __launch_bounds__(kBlock) void k_cp_fused(int8_t* __restrict__ b0, in
     const Range ro{rng_old[0], rng_old[1]};
     Range rn = ro;
     if (APPLY) rn = Range{rng_new[0], rng_new[1]};
+    const EncParams ep = enc_params(rn);
+    __shared__ DecodeTab tab;
+    decode_tab_fill(tab, ro);
     double lo = 2.0, hi = 0.0;
     for (uint64_t w = wave0; w < ntiles; w += nwaves) {
         const uint64_t base = tile_base(P, w, lane_off);
@@ -447,7 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_cp_fused(int8_t* __restrict__ b0, in
 #pragma unroll
             for (int j = 0; j < K; ++j)
                 if (s & (1 << j)) off += stride[j];
-            a[s] = decode(b0[base + off], b1[base + off], ro);
+            a[s] = decode_tab(tab, b0[base + off], b1[base + off]);
         }
         run_ops<double, K>(a, ops, P.n_ops, base, lane);
         // recompute the store addresses instead of keeping 2^K of them live
@@ -460,17 +617,17 @@ __global__ __launch_bounds__(kBlock) void k_cp_fused(int8_t* __restrict__ b0, in
             for (int j = 0; j < K; ++j)
                 if (s & (1 << j)) off += stride[j];
             JQ_SLOT_FENCE();
-            const double m = modulus(a[s]);
+            const double x = modulus2(a[s]);
             if (!APPLY) {
-                range_update(m, lo, hi);
+                range_update_x(x, lo, hi);
             } else {
-                const int c0 = encode_mod(m, rn);
+                const int c0 = encode_mod_x(x, ep);
                 b0[sbase + off] = (int8_t)c0;
-                b1[sbase + off] = (int8_t)(c0 == -128 ? 0 : encode_phase(a[s]));
+                b1[sbase + off] = (int8_t)(c0 == -128 ? 0 : encode_phase_fast(a[s]));
             }
         }
     }
-    if (!APPLY) range_flush(lo, hi, acc);
+    if (!APPLY) range_flush_x(lo, hi, acc);
 }
 
 // ------------------------------------------------------------ launchers --
@@ -491,6 +648,12 @@ void ensure_lut() {
         }
         JQ_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_cos), c, sizeof(c)));
         JQ_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_sin), s, sizeof(s)));
+        // least x with sqrt(x) >= 1 - kOneTol (sqrt correctly rounded)
+        const double T = 1.0 - kOneTol;
+        double x = T * T;
+        while (std::sqrt(x) >= T) x = std::nextafter(x, 0.0);
+        while (std::sqrt(x) < T) x = std::nextafter(x, 2.0);
+        JQ_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_x_one), &x, sizeof(x)));
     });
 }
 
@@ -595,15 +758,27 @@ void cp_apply_op(const CompactBufs& b, int n, const GateOp& op, hipStream_t st) 
         const int w = op.kind == OP_DENSE1 ? chunk_width(lb, ng) : 1;
         switch (op.kind) {
             case OP_DENSE1:
-                if (w == 16)
-                    hipLaunchKernelGGL(k_cp_dense1_w<16>, dim3(persistent_blocks(ng / 16)), dim3(kBlock), 0, st, b0,
-                                       b1, ng / 16, ins, lb, g, (const double*)b.range, rn, acc, apply);
-                else if (w == 4)
-                    hipLaunchKernelGGL(k_cp_dense1_w<4>, dim3(persistent_blocks(ng / 4)), dim3(kBlock), 0, st, b0, b1,
-                                       ng / 4, ins, lb, g, (const double*)b.range, rn, acc, apply);
-                else
-                    hipLaunchKernelGGL(k_cp_dense1_w<1>, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng,
-                                       ins, lb, g, (const double*)b.range, rn, acc, apply);
+                if (apply) {
+                    if (w == 16)
+                        hipLaunchKernelGGL((k_cp_dense1_w<16, 1>), dim3(persistent_blocks(ng / 16)), dim3(kBlock), 0,
+                                           st, b0, b1, ng / 16, ins, lb, g, (const double*)b.range, rn, acc);
+                    else if (w == 4)
+                        hipLaunchKernelGGL((k_cp_dense1_w<4, 1>), dim3(persistent_blocks(ng / 4)), dim3(kBlock), 0, st,
+                                           b0, b1, ng / 4, ins, lb, g, (const double*)b.range, rn, acc);
+                    else
+                        hipLaunchKernelGGL((k_cp_dense1_w<1, 1>), dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0,
+                                           b1, ng, ins, lb, g, (const double*)b.range, rn, acc);
+                } else {
+                    if (w == 16)
+                        hipLaunchKernelGGL((k_cp_dense1_w<16, 0>), dim3(persistent_blocks(ng / 16)), dim3(kBlock), 0,
+                                           st, b0, b1, ng / 16, ins, lb, g, (const double*)b.range, rn, acc);
+                    else if (w == 4)
+                        hipLaunchKernelGGL((k_cp_dense1_w<4, 0>), dim3(persistent_blocks(ng / 4)), dim3(kBlock), 0, st,
+                                           b0, b1, ng / 4, ins, lb, g, (const double*)b.range, rn, acc);
+                    else
+                        hipLaunchKernelGGL((k_cp_dense1_w<1, 0>), dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0,
+                                           b1, ng, ins, lb, g, (const double*)b.range, rn, acc);
+                }
                 break;
             case OP_DENSE2:
                 hipLaunchKernelGGL(k_cp_gate<OP_DENSE2>, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng,

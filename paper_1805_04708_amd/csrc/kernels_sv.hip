@@ -88,22 +88,22 @@ __global__ __launch_bounds__(kBlock) void k_permx(typename Vec<R>::T* __restrict
                                                    Ins ins, uint64_t tbit) {
     const uint64_t g0 = (uint64_t)blockIdx.x * (kIt * kBlock) + threadIdx.x;
     uint64_t i0[kIt];
-    typename Vec<R>::T a[kIt], b[kIt];
+    Cx<R> a[kIt], b[kIt];
 #pragma unroll
     for (int u = 0; u < kIt; ++u) {
         const uint64_t g = g0 + (uint64_t)u * kBlock;
         if (g < ngroups) {
             i0[u] = expand(g, ins);
-            a[u] = psi[i0[u]];
-            b[u] = psi[i0[u] | tbit];
+            a[u] = ld<R>(psi, i0[u]);
+            b[u] = ld<R>(psi, i0[u] | tbit);
         }
     }
 #pragma unroll
     for (int u = 0; u < kIt; ++u) {
         const uint64_t g = g0 + (uint64_t)u * kBlock;
         if (g < ngroups) {
-            psi[i0[u]] = b[u];
-            psi[i0[u] | tbit] = a[u];
+            st<R>(psi, i0[u], b[u]);
+            st<R>(psi, i0[u] | tbit, a[u]);
         }
     }
 }
