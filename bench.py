@@ -22,6 +22,31 @@ sys.path.insert(0, ROOT)
 
 METRIC = "gates/s + HBM GB/s (% peak) at N=30; p50/p99 latency on a served circuit mix"
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6   # vector FP64: 256 CUs x 128 flop/clk x 2.4 GHz
+PEAK_FP32_TFLOPS = 157.3  # vector FP32 (dual issue)
+# diagonal gates whose entries are +-1 (sign flips: no arithmetic)
+SIGN_ONLY = {"Z", "CZ"}
+DENSE_1Q = {"H", "Y", "MAT1", "U2", "U3", "+X", "-X", "+Y", "-Y", "U2H"}
+
+
+def circuit_flops(circuit, n):
+    """Algorithmic real flops of a circuit on 2^n amplitudes: a dense 2x2 on
+    the pairs of the controlled subspace costs 14 per amplitude (4 complex
+    products, 2 complex sums per pair), a diagonal phase 6 per amplitude it
+    multiplies, sign flips and permutations nothing."""
+    total = 0.0
+    for g in circuit:
+        name, qubits = g[0], g[1]
+        ctrl = len(g[3]) if len(g) > 3 else 0
+        if name in SIGN_ONLY or name in ("X", "CNOT", "TOFFOLI", "SWAP", "I"):
+            continue
+        if name in DENSE_1Q:
+            total += 14.0 * 2.0 ** (n - ctrl)
+        elif name in ("CP", "U"):
+            total += 6.0 * 2.0 ** (n - 2 - ctrl)
+        else:  # one-qubit phase gates (S, T, R, U1, RZ, ...)
+            total += 6.0 * 2.0 ** (n - 1 - ctrl)
+    return total
 
 
 def parse():
@@ -42,7 +67,7 @@ def parse():
     return p.parse_args()
 
 
-KERNEL_SOURCES = ["kernels_sv.hip", "device_common.hpp", "internal.hpp", "planner.cpp"]
+KERNEL_SOURCES = ["kernels_sv.hip", "fused_ops.hpp", "device_common.hpp", "internal.hpp", "planner.cpp"]
 
 
 def kernel_source_hash():
@@ -166,6 +191,16 @@ def main():
                      "traffic": traffic,
                      "alg_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms},
     }
+    if dom == "fused":
+        # the same kernel against the FP64 vector peak: algorithmic flops of
+        # the circuit spread over its fused launches
+        flops = circuit_flops(circuit, n) / (d["launches"] / args.steps)
+        out["roofline"]["alu"] = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12,
+                                  "peak": PEAK_FP64_TFLOPS if args.enc == "c128" else PEAK_FP32_TFLOPS,
+                                  "unit": "TFLOP/s",
+                                  "frac": flops / (avg_ms * 1e-3) / 1e12 /
+                                          (PEAK_FP64_TFLOPS if args.enc == "c128" else PEAK_FP32_TFLOPS),
+                                  "alg_flops_per_launch": flops}
 
     if not args.no_extras:
         out["per_target"] = per_target(state, n, bpa)
@@ -178,6 +213,7 @@ def main():
         out["batch"] = batch_extra()
         out["serve"] = serve_extra()
         out["compact"] = compact_extra()
+        out["compact_dense"] = compact_dense_extra()
         out["large_states"] = large_extra()
 
     if args.copy_calibration:
@@ -345,6 +381,51 @@ def compact_extra(n=30, layers=20):
     ref.close()
     return {"n": n, "gates": len(circ), "gates_per_s": len(circ) / dt, "seconds": dt,
             "fidelity_vs_c128": abs(ov) ** 2 / (nr * nc), "rel_l2_vs_c128": float(np.sqrt(max(diff2, 0) / nr))}
+
+
+def compact_dense_extra(n=30, layers=2, seed=11):
+    """Two layers of the layered Haar-U(2) + CZ circuit in the two-byte code:
+    quantisation after every gate (the paper's procedure) against once per
+    fused block; gates/s, kernel time and fidelity against the complex128
+    result of the same circuit on this GPU."""
+    import numpy as np
+    import torch
+    from paper_1805_04708_amd import jq
+    from paper_1805_04708_amd import workloads as W
+
+    circ = W.layered_u2_cz(n, layers, seed=seed)
+    arr = jq.gates(circ)
+    ref = jq.State(n, "c128")
+    ref.apply_circuit(arr)
+    ref.synchronize()
+    s = jq.State(n, "compact").set_stream(torch.cuda.current_stream())
+    out = {"n": n, "gates": len(circ), "workload": f"layered Haar-U(2) + CZ, {layers} layers, from |0...0>"}
+    for mode, cm in (("per_gate", jq.JQ_COMPACT_PER_GATE), ("per_block", jq.JQ_COMPACT_PER_BLOCK)):
+        _, blen, fused = jq.plan_schedule(n, "compact", arr, compact_mode=cm)
+        s.init(jq.JQ_INIT_ZERO)
+        s.synchronize()
+        s.profile(True)
+        t0 = time.perf_counter()
+        s.apply_circuit(arr, compact_mode=cm)
+        s.synchronize()
+        dt = time.perf_counter() - t0
+        st = s.profile_read()
+        s.profile(False)
+        ov, nr, nc = 0j, 0.0, 0.0
+        chunk = 1 << 24
+        for first in range(0, 1 << n, chunk):
+            a = s.amplitudes(first, chunk)
+            b = ref.amplitudes(first, chunk)
+            ov += np.vdot(b, a)
+            nr += float(np.vdot(b, b).real)
+            nc += float(np.vdot(a, a).real)
+        out[mode] = {"gates_per_s": len(circ) / dt, "seconds": dt, "blocks": len(blen), "fused_blocks": int(fused.sum()),
+                     "fidelity_vs_c128": abs(ov) ** 2 / (nr * nc),
+                     "kernels": {k: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"],
+                                     "gbps": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in st.items()}}
+    s.close()
+    ref.close()
+    return out
 
 
 def large_extra():

@@ -137,20 +137,26 @@ struct Dep {
 
 // Marginal distribution: block (bin, part) sums |a|^2 over the indices whose
 // selected bits spell `bin`, for its contiguous share of the other bits.
-template <class L>
+// With W > 1 (every selected qubit at position log2(W) or above) a thread
+// takes W consecutive amplitudes at a time (loader method modulus2_w).
+template <class L, int W>
 __global__ __launch_bounds__(kBlock) void k_probs(L ldr, InsN others, Dep sel, uint64_t n_others, uint32_t parts,
                                                    double* __restrict__ partial) {
     __shared__ double lds[kBlock / 64];
     ldr.prepare();
     const uint64_t bin = blockIdx.x / parts;
     const uint64_t part = blockIdx.x % parts;
-    const uint64_t chunk = (n_others + parts - 1) / parts;
+    const uint64_t n_w = n_others / W;
+    const uint64_t chunk = (n_w + parts - 1) / parts;
     const uint64_t lo = part * chunk;
-    const uint64_t hi = lo + chunk < n_others ? lo + chunk : n_others;
+    const uint64_t hi = lo + chunk < n_w ? lo + chunk : n_w;
     uint64_t binoff = 0;
     for (int m = 0; m < sel.nq; ++m) binoff |= ((bin >> m) & 1ull) << sel.q[m];
     double acc = 0.0;
-    for (uint64_t o = lo + threadIdx.x; o < hi; o += kBlock) acc += ldr.modulus2(expand_n(o, others) | binoff);
+    for (uint64_t o = lo + threadIdx.x; o < hi; o += kBlock) {
+        if constexpr (W == 1) acc += ldr.modulus2(expand_n(o, others) | binoff);
+        else acc += ldr.template modulus2_w<W>(expand_n(o * W, others) | binoff);
+    }
     const double s = block_sum(acc, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
@@ -207,7 +213,9 @@ Ins make_ins(uint64_t zero_bits, uint64_t ones);
 unsigned blocks_for(uint64_t items, uint64_t per_block);
 unsigned grid_stride_blocks(uint64_t dim);
 
-template <class L>
+// W: amplitudes per loader access in the main kernel (1, or 16 when the
+// loader has modulus2_w<16>; used only if no selected qubit is below 4)
+template <class L, int W = 1>
 void launch_probs(const L& ldr, int n, const int* qubits, int nq, double* out, double* partial, size_t cap,
                   hipStream_t st) {
     uint64_t selmask = 0;
@@ -234,8 +242,16 @@ void launch_probs(const L& ldr, int n, const int* qubits, int nq, double* out, d
     if (parts > want) parts = want;
     if (nbins * parts > cap) parts = cap / nbins;
     if (parts < 1) fail(JQ_EINVAL, "reduction scratch too small");
-    hipLaunchKernelGGL(k_probs<L>, dim3((unsigned)(nbins * parts)), dim3(kBlock), 0, st, ldr, others, d, n_others,
-                       (uint32_t)parts, partial);
+    bool wide = W > 1 && n_others >= (uint64_t)W * kBlock;
+    for (int m = 0; m < nq && wide; ++m) wide = (1ull << qubits[m]) >= (uint64_t)W;
+    if (wide) {
+        if constexpr (W > 1)
+            hipLaunchKernelGGL((k_probs<L, W>), dim3((unsigned)(nbins * parts)), dim3(kBlock), 0, st, ldr, others, d,
+                               n_others, (uint32_t)parts, partial);
+    } else {
+        hipLaunchKernelGGL((k_probs<L, 1>), dim3((unsigned)(nbins * parts)), dim3(kBlock), 0, st, ldr, others, d,
+                           n_others, (uint32_t)parts, partial);
+    }
     JQ_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(nbins, 64)), dim3(64), 0, st, partial, nbins, (uint32_t)parts,
                        out);

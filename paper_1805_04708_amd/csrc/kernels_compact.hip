@@ -388,19 +388,37 @@ __global__ void k_cp_scale_range(double* rng, double f) {
     }
 }
 
-// Reduction loader: decodes on the fly; the modulus comes from b0 alone.
+// Reduction loader: decodes through the per-block LDS tables; the modulus
+// comes from b0 alone.
 struct LoaderCP {
     const int8_t* b0;
     const int8_t* b1;
     const double* rng;
-    Range r;
-    __device__ void prepare() { r = Range{rng[0], rng[1]}; }
-    __device__ __forceinline__ Cx<double> amp(uint64_t i) const { return decode(b0[i], b1[i], r); }
+    const DecodeTab* tab;
+    // every thread of the block calls this (it ends with a barrier)
+    __device__ void prepare() {
+        __shared__ DecodeTab t;
+        decode_tab_fill(t, Range{rng[0], rng[1]});
+        tab = &t;
+    }
+    __device__ __forceinline__ Cx<double> amp(uint64_t i) const { return decode_tab(*tab, b0[i], b1[i]); }
     __device__ __forceinline__ double modulus2(uint64_t i) const {
-        const int c0 = b0[i];
-        if (c0 == -128) return 0.0;
-        const double m = c0 == 127 ? 1.0 : ((double)(c0 + 127) * (r.r1 - r.r0)) / 253.0 + r.r0;
+        const double m = tab->r[b0[i] + 128];
         return m * m;
+    }
+    // sum over the 16 amplitudes i..i+15 (i a multiple of 16), in order
+    template <int W>
+    __device__ __forceinline__ double modulus2_w(uint64_t i) const {
+        static_assert(W == 16, "16 codes per access");
+        const uint4 x = *reinterpret_cast<const uint4*>(b0 + i);
+        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const double m = tab->r[(int)(int8_t)(w[u >> 2] >> (8 * (u & 3))) + 128];
+            s += m * m;
+        }
+        return s;
     }
 };
 
@@ -862,7 +880,8 @@ void cp_apply_block(const CompactBufs& b, int n, const FPass& pass, int k_reg, i
 void cp_probabilities(const CompactBufs& b, int n, const int* qubits, int nq, double* out, double* partial, size_t cap,
                       hipStream_t st) {
     const uint64_t dim = 1ull << n;
-    launch_probs(LoaderCP{b.codes, b.codes + dim, b.range, {}}, n, qubits, nq, out, partial, cap, st);
+    ensure_lut();
+    launch_probs<LoaderCP, 16>(LoaderCP{b.codes, b.codes + dim, b.range, {}}, n, qubits, nq, out, partial, cap, st);
 }
 
 void cp_expectations(const CompactBufs& b, int n, double* out, double* partial, size_t cap, hipStream_t st) {
