@@ -62,8 +62,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--cpu-gates", type=int, default=3, help="gates of the circuit the CPU oracle times")
-    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                   help="also run a plain torch device copy of this many MiB (counter calibration)")
+    p.add_argument("--copy-calibration", type=int, default=4096, metavar="MIB",
+                   help="size of the plain torch device copy reported as the copy ceiling (and used to "
+                        "calibrate the traffic counters); 0 skips it")
     return p.parse_args()
 
 
@@ -217,17 +218,24 @@ def main():
         out["large_states"] = large_extra()
 
     if args.copy_calibration:
+        # a plain device copy: the practical streaming ceiling of this GPU,
+        # and the reference for scaling the HBM traffic counters
         nbytes = args.copy_calibration << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
         dst.copy_(src)
-        e1.record()
         torch.cuda.synchronize()
+        best = None
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            dst.copy_(src)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
         out["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes,
-                                   "gbps": 2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9}
+                                   "gbps": 2 * nbytes / (best * 1e-3) / 1e9, "frac_of_peak": 2 * nbytes / (best * 1e-3) / 1e9 / PEAK_HBM_GBS}
         del src, dst
 
     if not args.no_cpu_baseline:
