@@ -32,6 +32,9 @@ def lib():
         L.oq_norm2.restype = ctypes.c_double
         L.oq_probabilities.argtypes = [_dp, ctypes.c_int, _ip, ctypes.c_int, _dp]
         L.oq_expect_q.argtypes = [_dp, ctypes.c_int, _dp, _dp, _dp]
+        L.oq_project.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.oq_project.restype = ctypes.c_double
+        L.oq_measure.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
         L.oq_compact_decode.argtypes = [_bp, _bp, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, _dp]
         L.oq_compact_encode.argtypes = [_dp, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, _bp, _bp]
         L.oq_compact_range.argtypes = [_dp, ctypes.c_uint64, _dp, _dp]
@@ -133,6 +136,40 @@ def expect_q(psi, n):
     return qx, qy, qz
 
 
+def project(psi, n, q, v):
+    """Project qubit q onto |v> and renormalise in place (App. A, CLEAR /
+    SET); returns the probability p of |v> (0: the state is unchanged)."""
+    return lib().oq_project(_d(psi.view(np.float64)), n, q, v)
+
+
+def measure(psi, n, q, u):
+    """Projective measurement of qubit q (App. A, M) with the draw u in
+    [0, 1): outcome 1 iff u >= p0 / (p0 + p1).  Returns (outcome, p1)."""
+    p1 = ctypes.c_double(0.0)
+    out = lib().oq_measure(_d(psi.view(np.float64)), n, q, u, ctypes.byref(p1))
+    if out < 0:
+        raise ValueError("zero state")
+    return out, p1.value
+
+
+def run_program(psi, n, program, draws=()):
+    """Run gates and the instructions M, CLEAR and SET (App. A) in order.
+    draws supplies u for each M; returns the list of M outcomes.  CLEAR and
+    SET on an outcome of probability zero raise ValueError."""
+    draws = iter(draws)
+    outcomes = []
+    for ins in program:
+        name, q = ins[0], ins[1]
+        if name == "M":
+            outcomes.append(measure(psi, n, q[0], next(draws))[0])
+        elif name in ("CLEAR", "SET"):
+            if project(psi, n, q[0], 0 if name == "CLEAR" else 1) == 0.0:
+                raise ValueError(f"{name} {q[0]}: projection onto a zero-amplitude state")
+        else:
+            run(psi, n, [ins])
+    return outcomes
+
+
 def rel_l2(psi, ref):
     return float(np.linalg.norm(psi - ref) / np.linalg.norm(ref))
 
@@ -168,6 +205,23 @@ class CompactState:
         lib().oq_compact_decode(_b(self.b0), _b(self.b1), 1 << self.n, self.rng[0], self.rng[1],
                                 _d(psi.view(np.float64)))
         return psi
+
+    def project(self, q, v):
+        """Projection with renormalisation as a quantisation step (App. A,
+        CLEAR / SET; Sec. 4.1): decode, p = sum of |z|^2 over bit q = v, then
+        the diagonal gate sqrt(1/p)|v><v| on qubit q with a new range.
+        Returns p; on p == 0 the codes are unchanged."""
+        psi = self.decode()
+        b = 1 << q
+        idx = np.arange(1 << self.n)
+        keep = ((idx & b) != 0) == (v != 0)
+        p = float(np.sum(np.abs(psi[keep]) ** 2))
+        if p == 0.0:
+            return 0.0
+        f = 1.0 / np.sqrt(p)
+        d = (f, 0, 0, 0, 0, 0, 0, 0) if v == 0 else (0, 0, 0, 0, 0, 0, f, 0)
+        self.run([("MAT1", (q,), d)])
+        return p
 
     def run(self, circuit, blocks=None):
         """Apply a circuit.  blocks=None quantises after every gate (the

@@ -25,6 +25,57 @@
 #endif
 
 /*
+ * Projection of qubit q onto |v> with renormalisation (App. A, CLEAR for
+ * v = 0 and SET for v = 1: |v><v| on qubit q): p is the sum of |a_i|^2 over
+ * the indices whose bit q equals v; those amplitudes are divided by sqrt(p)
+ * and all others set to zero.  Returns p.  If p == 0 the projected state
+ * has zero amplitude (the paper's instructions fail then) and the state is
+ * left unchanged.
+ */
+double oq_project(double *psi, int n, int q, int v)
+{
+    const uint64_t dim = 1ull << n, b = 1ull << q;
+    double p = 0.0;
+    for (uint64_t i = 0; i < dim; i++)
+        if (((i & b) != 0) == (v != 0)) p = p + (psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1]);
+    if (p == 0.0) return 0.0;
+    const double f = 1.0 / sqrt(p);
+    for (uint64_t i = 0; i < dim; i++) {
+        if (((i & b) != 0) == (v != 0)) {
+            psi[2 * i] = psi[2 * i] * f;
+            psi[2 * i + 1] = psi[2 * i + 1] * f;
+        } else {
+            psi[2 * i] = 0.0;
+            psi[2 * i + 1] = 0.0;
+        }
+    }
+    return p;
+}
+
+/*
+ * Projective measurement of qubit q (App. A, M): p0 and p1 are the
+ * probabilities of outcomes 0 and 1 (sums of |a_i|^2 over bit q = 0, 1);
+ * the outcome is 1 when u >= p0 / (p0 + p1) for the caller's draw u in
+ * [0, 1), else 0, and the state is projected onto it as by oq_project.
+ * *p1_out receives p1 / (p0 + p1).  Returns the outcome, or -1 if the state
+ * is zero.
+ */
+int oq_measure(double *psi, int n, int q, double u, double *p1_out)
+{
+    const uint64_t dim = 1ull << n, b = 1ull << q;
+    double p0 = 0.0, p1 = 0.0;
+    for (uint64_t i = 0; i < dim; i++) {
+        double m = psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1];
+        if (i & b) p1 = p1 + m; else p0 = p0 + m;
+    }
+    if (p0 + p1 == 0.0) return -1;
+    *p1_out = p1 / (p0 + p1);
+    const int outcome = u >= p0 / (p0 + p1) ? 1 : 0;
+    oq_project(psi, n, q, outcome);
+    return outcome;
+}
+
+/*
  * Apply a 2^k x 2^k matrix to the target qubits targets[0..k-1] on the
  * subspace where every control qubit is 1 (Sec. 2, Eq. NUM2 for k = 1; the
  * groups of four and eight amplitudes for k = 2, 3).  Row/column index of
