@@ -203,6 +203,27 @@ int jq_expectations(jq_state *s, double *qx, double *qy, double *qz);
  * (r0, r1) and leaves the codes alone.  JQ_EZERO if the norm is zero. */
 int jq_renormalize(jq_state *s);
 
+/* ---- projection (App. A: CLEAR, SET, M) ------------------------------- */
+
+/* Project qubit `qubit` onto |value> (value 0: CLEAR, 1: SET) and
+ * renormalise: p = sum of |a_i|^2 over the basis states whose bit `qubit`
+ * equals value (FP64, as jq_probabilities); those amplitudes are divided by
+ * sqrt(p), all others become zero.  *p_out (may be NULL) receives p.
+ * JQ_EZERO if p is zero: the projection would leave no amplitude (the
+ * paper's instructions fail then) and the state is unchanged.  For the
+ * two-byte code the projection is one quantisation step with a new range.
+ * Synchronises (p decides what runs). */
+int jq_project(jq_state *s, int qubit, int value, double *p_out);
+
+/* Projective measurement of qubit `qubit` (App. A, M).  p0 and p1 are the
+ * FP64 probabilities of the two outcomes; the outcome is 1 when
+ * u >= p0 / (p0 + p1), else 0, where u in [0, 1) is a random number the
+ * caller draws (the library draws none); the state is then projected onto
+ * the outcome as by jq_project.  *outcome receives 0 or 1 and *p1_out (may
+ * be NULL) p1 / (p0 + p1).  JQ_EINVAL if u is outside [0, 1) or outcome is
+ * NULL, JQ_EZERO if the state is zero.  Synchronises. */
+int jq_measure(jq_state *s, int qubit, double u, int *outcome, double *p1_out);
+
 /* ---- amplitude transfer --------------------------------------------- */
 
 /* Copy amplitudes [first, first+count) to host as complex128 (decoded for

@@ -352,6 +352,22 @@ void state_norm_async(jq_state* s, double* pinned_out) {
     JQ_HIP(hipMemcpyAsync(pinned_out, scratch, sizeof(double), hipMemcpyDeviceToHost, s->stream));
 }
 
+
+// f |v><v| on qubit q as a diagonal op (entry v = f, the other entry 0)
+GateOp projector(int n, int q, int v, double f) {
+    jq_gate g;
+    std::memset(&g, 0, sizeof(g));
+    g.kind = JQ_DIAGONAL;
+    g.nq = 1;
+    g.qubits[0] = q;
+    g.m[2 * v] = f;
+    return canonicalize(g, n);
+}
+
+void check_qubit(const jq_state* s, int q, const char* who) {
+    if (q < 0 || q >= s->n) fail(JQ_EINVAL, std::string(who) + ": qubit out of range");
+}
+
 }  // namespace jq
 
 using namespace jq;
@@ -525,6 +541,36 @@ int jq_apply_circuit(jq_state* s, const jq_gate* gates, size_t count, const jq_e
             }
         }
         apply_ops(s, ops, plan_config(s->n, s->enc, opts));  // options validated before any work
+    });
+}
+
+int jq_project(jq_state* s, int qubit, int value, double* p_out) {
+    return guarded([&] {
+        check_state(s);
+        check_qubit(s, qubit, "jq_project");
+        if (value != 0 && value != 1) fail(JQ_EINVAL, "jq_project: value must be 0 or 1");
+        double p[2];
+        do_probabilities(s, &qubit, 1, p);
+        if (p_out) *p_out = p[value];
+        if (!(p[value] > 0.0)) fail(JQ_EZERO, "jq_project: the projection leaves no amplitude");
+        run_single(s, projector(s->n, qubit, value, 1.0 / std::sqrt(p[value])));
+    });
+}
+
+int jq_measure(jq_state* s, int qubit, double u, int* outcome, double* p1_out) {
+    return guarded([&] {
+        check_state(s);
+        check_qubit(s, qubit, "jq_measure");
+        if (!(u >= 0.0 && u < 1.0)) fail(JQ_EINVAL, "jq_measure: u must lie in [0, 1)");
+        if (!outcome) fail(JQ_EINVAL, "jq_measure: null outcome");
+        double p[2];
+        do_probabilities(s, &qubit, 1, p);
+        const double tot = p[0] + p[1];
+        if (!(tot > 0.0)) fail(JQ_EZERO, "jq_measure: zero state");
+        const int o = u >= p[0] / tot ? 1 : 0;
+        *outcome = o;
+        if (p1_out) *p1_out = p[1] / tot;
+        run_single(s, projector(s->n, qubit, o, 1.0 / std::sqrt(p[o])));
     });
 }
 

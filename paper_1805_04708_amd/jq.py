@@ -91,6 +91,8 @@ SIGNATURES = {
     "jq_probabilities": (ctypes.c_int, [_VP, _IP, ctypes.c_int, _DP]),
     "jq_expectations": (ctypes.c_int, [_VP, _DP, _DP, _DP]),
     "jq_renormalize": (ctypes.c_int, [_VP]),
+    "jq_project": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _DP]),
+    "jq_measure": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_double, _IP, _DP]),
     "jq_read_amplitudes": (ctypes.c_int, [_VP, _U64, _U64, _DP]),
     "jq_write_amplitudes": (ctypes.c_int, [_VP, _U64, _U64, _DP]),
     "jq_read_codes": (ctypes.c_int, [_VP, _U64, _U64, _BP, _BP, _DP]),
@@ -286,6 +288,40 @@ class State:
     def renormalize(self):
         check(lib().jq_renormalize(self.h))
         return self
+
+    def project(self, qubit, value):
+        """Project qubit onto |value> and renormalise (App. A, CLEAR / SET);
+        returns the probability of |value>.  JqError (JQ_EZERO) if it is 0."""
+        p = ctypes.c_double()
+        check(lib().jq_project(self.h, qubit, value, ctypes.byref(p)))
+        return p.value
+
+    def measure(self, qubit, u):
+        """Projective measurement (App. A, M) with the caller's draw u in
+        [0, 1): returns (outcome, p1)."""
+        out, p1 = ctypes.c_int(), ctypes.c_double()
+        check(lib().jq_measure(self.h, qubit, u, ctypes.byref(out), ctypes.byref(p1)))
+        return out.value, p1.value
+
+    def run_program(self, program, draws=()):
+        """Gates and the instructions M, CLEAR, SET in order; consecutive
+        gates go to jq_apply_circuit together.  Returns the M outcomes."""
+        draws = iter(draws)
+        outcomes, run = [], []
+        for ins in list(program) + [None]:
+            if ins is not None and ins[0] not in ("M", "CLEAR", "SET"):
+                run.append(ins)
+                continue
+            if run:
+                self.apply_circuit(run)
+                run = []
+            if ins is None:
+                break
+            if ins[0] == "M":
+                outcomes.append(self.measure(ins[1][0], next(draws))[0])
+            else:
+                self.project(ins[1][0], 0 if ins[0] == "CLEAR" else 1)
+        return outcomes
 
     def amplitudes(self, first=0, count=None):
         count = (1 << self.n) - first if count is None else count
