@@ -215,6 +215,7 @@ def main():
         out["serve"] = serve_extra()
         out["compact"] = compact_extra()
         out["compact_dense"] = compact_dense_extra()
+        out["shor"] = shor_extra()
         out["large_states"] = large_extra()
 
     if args.copy_calibration:
@@ -433,6 +434,36 @@ def compact_dense_extra(n=30, layers=2, seed=11):
                                      "gbps": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in st.items()}}
     s.close()
     ref.close()
+    return out
+
+
+def shor_extra(n=30, n_x=20, G=1007, y=529):
+    """Shor's algorithm on 30 qubits as in Table Shortab1: SHORBOX, the QFT on
+    the 20-qubit x-register and the expectation values of every qubit, timed
+    per encoding, with the largest deviation from the oracle's values (the
+    paper's two-byte run of this case took 348 s on an 8-core notebook)."""
+    import numpy as np
+    from oracle import shor as S
+    from paper_1805_04708_amd import jq
+    from paper_1805_04708_amd import workloads as W
+
+    ex, ey, ez = S.qft_expectations(n_x, G, y)
+    circ = jq.gates(W.qft(n_x))
+    out = {"n": n, "n_x": n_x, "G": G, "y": y, "qft_gates": circ[1]}
+    for enc, cm in (("c128", 0), ("c64", 0), ("compact", jq.JQ_COMPACT_PER_GATE),
+                    ("compact_per_block", jq.JQ_COMPACT_PER_BLOCK)):
+        s = jq.State(n, "compact" if enc.startswith("compact") else enc)
+        s.shorbox(n_x, G, y)
+        s.apply_circuit(circ, compact_mode=cm)
+        s.synchronize()
+        t0 = time.perf_counter()
+        s.shorbox(n_x, G, y)
+        s.apply_circuit(circ, compact_mode=cm)
+        qx, qy, qz = (v[:n_x] for v in s.expectations())
+        dt = time.perf_counter() - t0
+        s.close()
+        out[enc] = {"seconds": dt, "max_dev_from_exact": float(max(np.max(np.abs(qx - ex)), np.max(np.abs(qy - ey)),
+                                                                   np.max(np.abs(qz - ez))))}
     return out
 
 

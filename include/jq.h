@@ -124,6 +124,14 @@ int jq_state_destroy(jq_state *s);
  * (basis < 2^N).  Asynchronous. */
 int jq_state_init(jq_state *s, jq_init mode, uint64_t basis);
 
+/* Set the state to the SHORBOX state of App. A (Sec. 5.3):
+ * 2^(-n_x/2) sum over x = 0 .. 2^n_x - 1 of |x>|y^x mod G>, the x-register
+ * on qubits 0 .. n_x-1 (x's least significant bit on qubit 0) and the
+ * f-register on the qubits above.  Needs 1 <= n_x < N, n_x <= 40,
+ * 2 <= G < 2^32, G <= 2^(N - n_x) and 1 < y < G (y coprime to G for
+ * Shor's algorithm; not checked), else JQ_EINVAL.  Asynchronous. */
+int jq_shorbox(jq_state *s, int n_x, uint64_t G, uint64_t y);
+
 /* Number of qubits, encoding, and device bytes held (host outputs; any may
  * be NULL). */
 int jq_state_info(const jq_state *s, int *n_qubits, int *encoding, uint64_t *bytes);

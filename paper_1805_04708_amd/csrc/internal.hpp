@@ -160,6 +160,8 @@ inline int bytes_per_amp(int enc) { return enc == JQ_C128 ? 16 : enc == JQ_C64 ?
 // state-vector (c128 / c64) launchers; psi is the device buffer
 void sv_init(int enc, void* psi, int n, int mode, uint64_t basis, hipStream_t st);
 void sv_apply_op(int enc, void* psi, int n, const GateOp& op, hipStream_t st);
+// SHORBOX (App. A): 2^(-n_x/2) sum_x |x>|y^x mod G>, x on the n_x low qubits
+void sv_shorbox(int enc, void* psi, int n, int n_x, uint64_t G, uint64_t y, hipStream_t st);
 void sv_apply_fused(int enc, void* psi, int n, const FPass& pass, int k_reg, int fixed_lane_bits,
                     hipStream_t st);
 // FP64 marginal distribution; out_dev receives 2^nq doubles (device)
@@ -182,6 +184,7 @@ struct CompactBufs {
 };
 void cp_init(const CompactBufs& b, int n, int mode, uint64_t basis, hipStream_t st);
 void cp_apply_op(const CompactBufs& b, int n, const GateOp& op, hipStream_t st);
+void cp_shorbox(const CompactBufs& b, int n, int n_x, uint64_t G, uint64_t y, hipStream_t st);
 // lane bits of the compact fused pass fixed to index bits 0..F-1 (each
 // code plane is read in runs of 2^F bytes)
 constexpr int kCpFixedLaneBits = 6;

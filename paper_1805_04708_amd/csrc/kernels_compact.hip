@@ -648,6 +648,27 @@ __global__ __launch_bounds__(kBlock) void k_cp_fused(int8_t* __restrict__ b0, in
     if (!APPLY) range_flush_x(lo, hi, acc);
 }
 
+// SHORBOX in the two-byte code: every amplitude of the state has modulus
+// 2^(-n_x/2) or 0, so the range is (a, a) and each non-zero code is -127
+// with phase code 0 (the planes have been cleared to zero amplitudes).
+__global__ __launch_bounds__(kBlock) void k_cp_shorbox(int8_t* __restrict__ b0, int n_x, uint64_t G, uint64_t y,
+                                                        double* rng, double a) {
+    const uint64_t nx = 1ull << n_x;
+    for (uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x; x < nx; x += (uint64_t)gridDim.x * kBlock) {
+        uint64_t r = 1 % G, b = y % G, e = x;
+        while (e) {
+            if (e & 1) r = r * b % G;
+            b = b * b % G;
+            e >>= 1;
+        }
+        b0[x + (r << n_x)] = -127;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        rng[0] = a;
+        rng[1] = a;
+    }
+}
+
 // ------------------------------------------------------------ launchers --
 
 namespace {
@@ -710,6 +731,14 @@ void cp_init(const CompactBufs& b, int n, int mode, uint64_t basis, hipStream_t 
     hipLaunchKernelGGL(k_cp_init, dim3(persistent_blocks(dim)), dim3(kBlock), 0, st, b.codes, b.codes + dim, dim, mode,
                        basis, b.range, uni);
     hipLaunchKernelGGL(k_cp_acc_reset, dim3(1), dim3(64), 0, st, (unsigned long long*)b.acc);
+    JQ_HIP(hipGetLastError());
+}
+
+void cp_shorbox(const CompactBufs& b, int n, int n_x, uint64_t G, uint64_t y, hipStream_t st) {
+    cp_init(b, n, JQ_INIT_BASIS, ~0ull, st);  // all codes -128 (zero), range (0, 0)
+    const uint64_t nx = 1ull << n_x;
+    hipLaunchKernelGGL(k_cp_shorbox, dim3(persistent_blocks(nx)), dim3(kBlock), 0, st, b.codes, n_x, G, y, b.range,
+                       uniform_amplitude(n_x));
     JQ_HIP(hipGetLastError());
 }
 

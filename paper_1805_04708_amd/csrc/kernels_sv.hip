@@ -196,6 +196,32 @@ __global__ __launch_bounds__(kBlock) void k_from_c128(typename Vec<R>::T* __rest
     }
 }
 
+// SHORBOX (App. A): amplitude a at index x + 2^n_x (y^x mod G) for every x
+// of the n_x-qubit x-register; the state has been zeroed before.  Each
+// thread raises y to its own x by square-and-multiply (G < 2^32, so every
+// product fits in 64 bits).
+__device__ __forceinline__ uint64_t pow_mod(uint64_t y, uint64_t e, uint64_t G) {
+    uint64_t r = 1 % G, b = y % G;
+    while (e) {
+        if (e & 1) r = r * b % G;
+        b = b * b % G;
+        e >>= 1;
+    }
+    return r;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_shorbox(typename Vec<R>::T* __restrict__ psi, int n_x, uint64_t G,
+                                                     uint64_t y, double a) {
+    const uint64_t nx = 1ull << n_x;
+    for (uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x; x < nx; x += (uint64_t)gridDim.x * kBlock) {
+        typename Vec<R>::T v;
+        v.x = (R)a;
+        v.y = (R)0;
+        psi[x + (pow_mod(y, x, G) << n_x)] = v;
+    }
+}
+
 // ---------------------------------------------------------- reductions --
 
 // Loader for the reduction kernels: amplitudes as FP64.
@@ -349,6 +375,19 @@ void sv_init(int enc, void* psi, int n, int mode, uint64_t basis, hipStream_t st
     else
         hipLaunchKernelGGL(k_init<float>, dim3(grid_stride_blocks(dim)), dim3(kBlock), 0, st, (float2*)psi, dim, mode,
                            basis, v);
+    JQ_HIP(hipGetLastError());
+}
+
+void sv_shorbox(int enc, void* psi, int n, int n_x, uint64_t G, uint64_t y, hipStream_t st) {
+    sv_init(enc, psi, n, JQ_INIT_BASIS, ~0ull, st);  // no basis state matches: all zero
+    const uint64_t nx = 1ull << n_x;
+    const double a = uniform_amplitude(n_x);
+    if (enc == JQ_C128)
+        hipLaunchKernelGGL(k_shorbox<double>, dim3(grid_stride_blocks(nx)), dim3(kBlock), 0, st, (double2*)psi, n_x, G,
+                           y, a);
+    else
+        hipLaunchKernelGGL(k_shorbox<float>, dim3(grid_stride_blocks(nx)), dim3(kBlock), 0, st, (float2*)psi, n_x, G,
+                           y, a);
     JQ_HIP(hipGetLastError());
 }
 

@@ -447,6 +447,19 @@ int jq_state_init(jq_state* s, jq_init mode, uint64_t basis) {
     });
 }
 
+int jq_shorbox(jq_state* s, int n_x, uint64_t G, uint64_t y) {
+    return guarded([&] {
+        check_state(s);
+        if (n_x < 1 || n_x >= s->n || n_x > 40) fail(JQ_EINVAL, "jq_shorbox: need 1 <= n_x < N and n_x <= 40");
+        if (G < 2 || G >= (1ull << 32)) fail(JQ_EINVAL, "jq_shorbox: need 2 <= G < 2^32");
+        if (s->n - n_x < 64 && G > (1ull << (s->n - n_x)))
+            fail(JQ_EINVAL, "jq_shorbox: the f-register cannot hold values up to G - 1");
+        if (y <= 1 || y >= G) fail(JQ_EINVAL, "jq_shorbox: need 1 < y < G");
+        if (s->enc == JQ_COMPACT) cp_shorbox(compact_bufs(s), s->n, n_x, G, y, s->stream);
+        else sv_shorbox(s->enc, s->buf, s->n, n_x, G, y, s->stream);
+    });
+}
+
 int jq_state_info(const jq_state* s, int* n, int* enc, uint64_t* bytes) {
     return guarded([&] {
         check_state(s);

@@ -76,6 +76,7 @@ SIGNATURES = {
     "jq_state_destroy": (ctypes.c_int, [_VP]),
     "jq_state_init": (ctypes.c_int, [_VP, ctypes.c_int, _U64]),
     "jq_state_info": (ctypes.c_int, [_VP, _IP, _IP, ctypes.POINTER(_U64)]),
+    "jq_shorbox": (ctypes.c_int, [_VP, ctypes.c_int, _U64, _U64]),
     "jq_state_device_ptr": (ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),
     "jq_set_stream": (ctypes.c_int, [_VP, _VP]),
     "jq_synchronize": (ctypes.c_int, [_VP]),
@@ -287,6 +288,11 @@ class State:
 
     def renormalize(self):
         check(lib().jq_renormalize(self.h))
+        return self
+
+    def shorbox(self, n_x, G, y):
+        """SHORBOX (App. A): 2^(-n_x/2) sum_x |x>|y^x mod G>, x on the low n_x qubits."""
+        check(lib().jq_shorbox(self.h, n_x, G, y))
         return self
 
     def project(self, qubit, value):
