@@ -35,6 +35,7 @@ def lib():
         L.oq_project.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.oq_project.restype = ctypes.c_double
         L.oq_measure.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
+        L.oq_sample.argtypes = [_dp, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
         L.oq_compact_decode.argtypes = [_bp, _bp, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, _dp]
         L.oq_compact_encode.argtypes = [_dp, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, _bp, _bp]
         L.oq_compact_range.argtypes = [_dp, ctypes.c_uint64, _dp, _dp]
@@ -150,6 +151,23 @@ def measure(psi, n, q, u):
     if out < 0:
         raise ValueError("zero state")
     return out, p1.value
+
+
+def sample(psi, n, u):
+    """Basis states drawn from |a|^2 (App. A, GENERATE EVENTS) for the draws
+    u in [0, 1): event k is the least i whose cumulative probability (in
+    index order) exceeds u_k times the total."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(max(1, len(u)), dtype=np.uint64)
+    if lib().oq_sample(_d(psi.view(np.float64)), n, _d(u), len(u),
+                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))):
+        raise ValueError("zero state")
+    return out[:len(u)]
+
+
+def cdf(psi):
+    """Cumulative probabilities in index order (the sums oq_sample uses)."""
+    return np.cumsum(np.abs(psi) ** 2)
 
 
 def run_program(psi, n, program, draws=()):

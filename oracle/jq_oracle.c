@@ -76,6 +76,36 @@ int oq_measure(double *psi, int n, int q, double u, double *p1_out)
 }
 
 /*
+ * Sampling of basis states (App. A, GENERATE EVENTS): with the cumulative
+ * sums C_i = p_0 + ... + p_i of p_i = |a_i|^2 (accumulated in index order)
+ * and the caller's draws u_k in [0, 1), event k is the least i with
+ * C_i > u_k * C_(2^N - 1).  Returns 0, or -1 for a zero state.
+ */
+int oq_sample(const double *psi, int n, const double *u, int count, uint64_t *out)
+{
+    const uint64_t dim = 1ull << n;
+    double *cdf = (double *)malloc(dim * sizeof(double));
+    if (!cdf) return -1;
+    double c = 0.0;
+    for (uint64_t i = 0; i < dim; i++) {
+        c = c + (psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1]);
+        cdf[i] = c;
+    }
+    if (c == 0.0) { free(cdf); return -1; }
+    for (int k = 0; k < count; k++) {
+        const double t = u[k] * c;
+        uint64_t lo = 0, hi = dim - 1;  /* cdf[hi] = c > t */
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo) / 2;
+            if (cdf[mid] > t) hi = mid; else lo = mid + 1;
+        }
+        out[k] = lo;
+    }
+    free(cdf);
+    return 0;
+}
+
+/*
  * Apply a 2^k x 2^k matrix to the target qubits targets[0..k-1] on the
  * subspace where every control qubit is 1 (Sec. 2, Eq. NUM2 for k = 1; the
  * groups of four and eight amplitudes for k = 2, 3).  Row/column index of

@@ -1,10 +1,13 @@
-"""Pins of the oracle's projection layer (App. A: M, CLEAR, SET) on the CPU.
+"""Pins of the oracle's projection layer (App. A: M, CLEAR, SET) and of its
+sampler (GENERATE EVENTS) on the CPU.
 
 The App. B error-correction example fixes everything: its syndrome
 measurements have certain outcomes, so the printed expectation values after
 the corrections, CLEAR and SET do not depend on the random draws.  The
 projection itself is checked against the projector |v><v| built as a dense
-matrix, and the measurement rule against its threshold definition."""
+matrix, and the measurement rule against its threshold definition.  The
+sampler is checked against closed forms (uniform, basis and GHZ states) and
+a brute-force scan of the running sum."""
 import json
 import math
 import os
@@ -110,3 +113,48 @@ def test_compact_projection_of_uniform_state_is_exact():
     assert st.rng[0] == st.rng[1] and abs(st.rng[0] - 2.0 ** (-(n - 1) / 2)) < 1e-16
     amp = st.decode()
     assert np.max(np.abs(amp[kept] - 2.0 ** (-(n - 1) / 2))) < 1e-16 and np.all(amp[~kept] == 0)
+
+
+# -- GENERATE EVENTS (App. A): inverse-CDF sampling with the caller's draws --
+
+def test_sample_uniform_state_is_floor_of_u():
+    # p_i = 2^-N exactly, so the cumulative sums are exact and event = floor(u 2^N)
+    n = 10
+    u = np.concatenate([[0.0, 1 - 2.0 ** -40, 0.25, 0.5, 0.75], np.random.default_rng(1).random(500)])
+    got = O.sample(O.uniform_state(n), n, u)
+    assert np.array_equal(got, np.floor(u * 2 ** n).astype(np.uint64))
+
+
+def test_sample_basis_and_ghz_states():
+    n = 7
+    u = np.random.default_rng(2).random(200)
+    assert np.all(O.sample(O.basis_state(n, 77), n, u) == 77)
+    ghz = O.run(O.zero_state(n), n, [("H", (0,), ())] + [("CNOT", (q, q + 1), ()) for q in range(n - 1)])
+    u = u[np.abs(u - 0.5) > 1e-9]
+    got = O.sample(ghz, n, u)
+    assert np.array_equal(got, np.where(u < 0.5, 0, (1 << n) - 1).astype(np.uint64))
+
+
+def test_sample_is_the_first_index_past_the_target():
+    # brute force: scan the running sum in index order
+    rng = np.random.default_rng(3)
+    n = 6
+    psi = rand_state(rng, n)
+    psi[rng.random(1 << n) < 0.3] = 0  # zero-probability states are never drawn
+    u = rng.random(300)
+    got = O.sample(psi, n, u)
+    p = psi.real * psi.real + psi.imag * psi.imag
+    total = 0.0
+    for x in p:
+        total = total + x
+    for k in range(len(u)):
+        t, c = u[k] * total, 0.0
+        for i in range(1 << n):
+            c = c + p[i]
+            if c > t:
+                break
+        assert got[k] == i and p[i] > 0
+    # frequencies on a fine grid of draws are the probabilities
+    grid = (np.arange(20000) + 0.5) / 20000
+    counts = np.bincount(O.sample(psi, n, grid).astype(np.int64), minlength=1 << n)
+    assert np.max(np.abs(counts / len(grid) - p / p.sum())) <= 1.0 / len(grid)
