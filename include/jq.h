@@ -211,6 +211,15 @@ int jq_expectations(jq_state *s, double *qx, double *qy, double *qz);
  * (r0, r1) and leaves the codes alone.  JQ_EZERO if the norm is zero. */
 int jq_renormalize(jq_state *s);
 
+/* Draw basis states from the distribution |a_i|^2 (App. A, GENERATE
+ * EVENTS), leaving the state unchanged.  u[0..count-1] (host) are draws in
+ * [0, 1) the caller supplies (the library draws no random numbers); out[k]
+ * (host) receives the least i whose cumulative probability (FP64, summed in
+ * index order in fixed blocks) exceeds u[k] times the total.  Indices of
+ * zero probability are never returned.  JQ_EINVAL for a draw outside
+ * [0, 1), JQ_EZERO for a zero state.  Synchronises. */
+int jq_sample(jq_state *s, const double *u, size_t count, uint64_t *out);
+
 /* ---- projection (App. A: CLEAR, SET, M) ------------------------------- */
 
 /* Project qubit `qubit` onto |value> (value 0: CLEAR, 1: SET) and

@@ -206,6 +206,113 @@ __global__ __launch_bounds__(kBlock) void k_expect(L ldr, Ins ins, uint64_t qbit
     }
 }
 
+// ------------------------------------------------------------ sampling --
+//
+// Inverse-CDF sampling of basis states (App. A, GENERATE EVENTS).  The
+// cumulative probability of amplitude i is a sum of sums at four levels:
+// 16 amplitudes per thread, 256 threads per block (4096 amplitudes), 4096
+// blocks per super-block, then the super-blocks; every level's total is the
+// sequential sum (from 0.0) of its children's totals, and the running value
+// at i is SP[sb] + (BP[b] + (T_t + w_k)).  At each level's end the running
+// value therefore equals the next start exactly, so it never decreases and
+// the search for the first value above a target ends inside the block the
+// prefix search chose.
+
+
+template <class L>
+__global__ __launch_bounds__(kBlock) void k_sample_block_sums(L ldr, uint64_t dim, double* __restrict__ bsum) {
+    __shared__ double cs[kBlock];
+    ldr.prepare();
+    const uint64_t first = ((uint64_t)blockIdx.x << kSampleBlockBits) + (uint64_t)threadIdx.x * kSampleLeaf;
+    double w = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSampleLeaf; ++k)
+        if (first + k < dim) w = w + ldr.modulus2(first + k);
+    cs[threadIdx.x] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int j = 0; j < kBlock; ++j) t = t + cs[j];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+// one thread per super-block: exclusive running sums of its blocks
+__global__ void k_sample_block_prefix(const double* __restrict__ bsum, uint64_t nblocks, uint64_t nsuper,
+                                      double* __restrict__ bp, double* __restrict__ ssum);
+// one thread: exclusive running sums of the super-blocks, then the total
+__global__ void k_sample_super_prefix(const double* __restrict__ ssum, uint64_t nsuper, double* __restrict__ sp);
+
+// One workgroup per draw (grid-stride over the draws).
+template <class L>
+__global__ __launch_bounds__(kBlock) void k_sample(L ldr, uint64_t dim, const double* __restrict__ sp,
+                                                    uint64_t nsuper, const double* __restrict__ bp, uint64_t nblocks,
+                                                    const double* __restrict__ u, uint64_t count,
+                                                    uint64_t* __restrict__ out) {
+    __shared__ double pv[kBlock * kSampleLeaf];
+    __shared__ double cs[kBlock];
+    ldr.prepare();
+    const double total = sp[nsuper];
+    for (uint64_t d = blockIdx.x; d < count; d += gridDim.x) {
+        const double target = u[d] * total;
+        // last super-block, then last block in it, whose start is <= target
+        uint64_t lo = 0, hi = nsuper - 1;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi + 1) / 2;
+            if (sp[mid] <= target) lo = mid; else hi = mid - 1;
+        }
+        const uint64_t sb = lo;
+        const double s0 = sp[sb];
+        uint64_t blo = sb << kSampleSuperBits;
+        uint64_t bhi = blo + (1ull << kSampleSuperBits) < nblocks ? blo + (1ull << kSampleSuperBits) - 1 : nblocks - 1;
+        while (blo < bhi) {
+            const uint64_t mid = (blo + bhi + 1) / 2;
+            if (s0 + bp[mid] <= target) blo = mid; else bhi = mid - 1;
+        }
+        const uint64_t blk = blo;
+        const double b0 = bp[blk];
+        const uint64_t first = (blk << kSampleBlockBits) + (uint64_t)threadIdx.x * kSampleLeaf;
+        double w = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSampleLeaf; ++k) {
+            const double p = first + k < dim ? ldr.modulus2(first + k) : 0.0;
+            pv[threadIdx.x * kSampleLeaf + k] = p;
+            w = w + p;
+        }
+        cs[threadIdx.x] = w;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t idx = ~0ull;
+            double t = 0.0;
+            for (int j = 0; j < kBlock && idx == ~0ull; ++j) {
+                if (s0 + (b0 + (t + cs[j])) > target) {
+                    double wk = 0.0;
+                    for (int k = 0; k < kSampleLeaf; ++k) {
+                        wk = wk + pv[j * kSampleLeaf + k];
+                        if (s0 + (b0 + (t + wk)) > target) {
+                            idx = (blk << kSampleBlockBits) + (uint64_t)(j * kSampleLeaf + k);
+                            break;
+                        }
+                    }
+                }
+                t = t + cs[j];
+            }
+            if (idx == ~0ull) {
+                // target at the very top (u rounded up to the total): the last
+                // amplitude of the block with non-zero probability
+                idx = blk << kSampleBlockBits;
+                for (int e = kBlock * kSampleLeaf - 1; e >= 0; --e)
+                    if (pv[e] > 0.0) {
+                        idx = (blk << kSampleBlockBits) + (uint64_t)e;
+                        break;
+                    }
+            }
+            out[d] = idx;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_expect_final(const double* __restrict__ partial, uint32_t parts, int q, int n,
                                double* __restrict__ out);
 
@@ -255,6 +362,29 @@ void launch_probs(const L& ldr, int n, const int* qubits, int nq, double* out, d
     JQ_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(nbins, 64)), dim3(64), 0, st, partial, nbins, (uint32_t)parts,
                        out);
+    JQ_HIP(hipGetLastError());
+}
+
+// u_dev: count draws in [0, 1) (device); out_dev: count indices (device).
+template <class L>
+void launch_sample(const L& ldr, int n, const double* u_dev, uint64_t count, uint64_t* out_dev, double* scratch,
+                   hipStream_t st) {
+    const uint64_t dim = 1ull << n;
+    const uint64_t nblocks = n > kSampleBlockBits ? 1ull << (n - kSampleBlockBits) : 1;
+    const uint64_t nsuper = (nblocks + (1ull << kSampleSuperBits) - 1) >> kSampleSuperBits;
+    double* bsum = scratch;
+    double* bp = bsum + nblocks;
+    double* ssum = bp + nblocks;
+    double* sp = ssum + nsuper;
+    hipLaunchKernelGGL(k_sample_block_sums<L>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, ldr, dim, bsum);
+    hipLaunchKernelGGL(k_sample_block_prefix, dim3(blocks_for(nsuper, 64)), dim3(64), 0, st, bsum, nblocks, nsuper,
+                       bp, ssum);
+    hipLaunchKernelGGL(k_sample_super_prefix, dim3(1), dim3(64), 0, st, ssum, nsuper, sp);
+    if (count) {
+        const unsigned grid = (unsigned)(count < 16384 ? count : 16384);
+        hipLaunchKernelGGL(k_sample<L>, dim3(grid), dim3(kBlock), 0, st, ldr, dim, sp, nsuper, bp, nblocks, u_dev,
+                           count, out_dev);
+    }
     JQ_HIP(hipGetLastError());
 }
 

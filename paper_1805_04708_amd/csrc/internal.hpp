@@ -171,6 +171,24 @@ size_t probabilities_partial_count(int n, int nq);
 void sv_expectations(int enc, const void* psi, int n, double* out_dev /* 3*n */, double* partial_dev,
                      size_t partial_cap, hipStream_t st);
 void sv_scale(int enc, void* psi, int n, double factor, hipStream_t st);
+// Sampling hierarchy: 16 amplitudes per thread, 4096 per block, 4096 blocks
+// per super-block.
+constexpr int kSampleLeaf = 16;
+constexpr int kSampleBlockBits = 12;
+constexpr int kSampleSuperBits = 12;
+
+// Scratch of the sampler: nblocks (block sums) + nblocks (block prefixes) +
+// nsuper (super-block sums) + nsuper + 1 (super-block prefixes) doubles.
+inline size_t sample_scratch_doubles(int n) {
+    const uint64_t nblocks = n > kSampleBlockBits ? 1ull << (n - kSampleBlockBits) : 1;
+    const uint64_t nsuper = (nblocks + (1ull << kSampleSuperBits) - 1) >> kSampleSuperBits;
+    return 2 * nblocks + 2 * nsuper + 1;
+}
+
+// basis states drawn from |a|^2 for the draws u (device arrays; scratch holds
+// sample_scratch_doubles(n) doubles)
+void sv_sample(int enc, const void* psi, int n, const double* u, uint64_t count, uint64_t* out, double* scratch,
+               hipStream_t st);
 // convert [first, first+count) to complex128 into dst (device)
 void sv_to_c128(int enc, const void* psi, uint64_t first, uint64_t count, double* dst, hipStream_t st);
 void sv_from_c128(int enc, void* psi, uint64_t first, uint64_t count, const double* src, hipStream_t st);
@@ -197,6 +215,8 @@ void cp_probabilities(const CompactBufs& b, int n, const int* qubits, int nq, do
 void cp_expectations(const CompactBufs& b, int n, double* out_dev, double* partial_dev, size_t cap,
                      hipStream_t st);
 void cp_scale_range(const CompactBufs& b, double factor, hipStream_t st);
+void cp_sample(const CompactBufs& b, int n, const double* u, uint64_t count, uint64_t* out, double* scratch,
+               hipStream_t st);
 void cp_to_c128(const CompactBufs& b, int n, uint64_t first, uint64_t count, double* dst,
                 hipStream_t st);
 void cp_encode_from_c128(const CompactBufs& b, int n, const double* src, hipStream_t st);

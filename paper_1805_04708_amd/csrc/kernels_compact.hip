@@ -913,6 +913,13 @@ void cp_probabilities(const CompactBufs& b, int n, const int* qubits, int nq, do
     launch_probs<LoaderCP, 16>(LoaderCP{b.codes, b.codes + dim, b.range, {}}, n, qubits, nq, out, partial, cap, st);
 }
 
+void cp_sample(const CompactBufs& b, int n, const double* u, uint64_t count, uint64_t* out, double* scratch,
+               hipStream_t st) {
+    ensure_lut();
+    const uint64_t dim = 1ull << n;
+    launch_sample(LoaderCP{b.codes, b.codes + dim, b.range, {}}, n, u, count, out, scratch, st);
+}
+
 void cp_expectations(const CompactBufs& b, int n, double* out, double* partial, size_t cap, hipStream_t st) {
     ensure_lut();
     const uint64_t dim = 1ull << n;

@@ -240,6 +240,31 @@ struct LoaderSV {
     }
 };
 
+// Sampling prefixes (see device_common.hpp): one thread per super-block
+__global__ void k_sample_block_prefix(const double* __restrict__ bsum, uint64_t nblocks, uint64_t nsuper,
+                                      double* __restrict__ bp, double* __restrict__ ssum) {
+    const uint64_t sb = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sb >= nsuper) return;
+    const uint64_t lo = sb << kSampleSuperBits;
+    const uint64_t hi = lo + (1ull << kSampleSuperBits) < nblocks ? lo + (1ull << kSampleSuperBits) : nblocks;
+    double r = 0.0;
+    for (uint64_t b = lo; b < hi; ++b) {
+        bp[b] = r;
+        r = r + bsum[b];
+    }
+    ssum[sb] = r;
+}
+
+__global__ void k_sample_super_prefix(const double* __restrict__ ssum, uint64_t nsuper, double* __restrict__ sp) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double r = 0.0;
+    for (uint64_t i = 0; i < nsuper; ++i) {
+        sp[i] = r;
+        r = r + ssum[i];
+    }
+    sp[nsuper] = r;
+}
+
 __global__ void k_sum_parts(const double* __restrict__ partial, uint64_t nbins, uint32_t parts,
                             double* __restrict__ out) {
     const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -410,6 +435,12 @@ void sv_probabilities(int enc, const void* psi, int n, const int* qubits, int nq
                       size_t cap, hipStream_t st) {
     if (enc == JQ_C128) launch_probs(LoaderSV<double>{(const double2*)psi}, n, qubits, nq, out, partial, cap, st);
     else launch_probs(LoaderSV<float>{(const float2*)psi}, n, qubits, nq, out, partial, cap, st);
+}
+
+void sv_sample(int enc, const void* psi, int n, const double* u, uint64_t count, uint64_t* out, double* scratch,
+               hipStream_t st) {
+    if (enc == JQ_C128) launch_sample(LoaderSV<double>{(const double2*)psi}, n, u, count, out, scratch, st);
+    else launch_sample(LoaderSV<float>{(const float2*)psi}, n, u, count, out, scratch, st);
 }
 
 void sv_expectations(int enc, const void* psi, int n, double* out, double* partial, size_t cap, hipStream_t st) {

@@ -557,6 +557,42 @@ int jq_apply_circuit(jq_state* s, const jq_gate* gates, size_t count, const jq_e
     });
 }
 
+int jq_sample(jq_state* s, const double* u, size_t count, uint64_t* out) {
+    return guarded([&] {
+        check_state(s);
+        if (count && (!u || !out)) fail(JQ_EINVAL, "jq_sample: null array");
+        if (s->n > 43) fail(JQ_EUNSUPPORTED, "jq_sample: more than 2^43 amplitudes");
+        for (size_t k = 0; k < count; ++k)
+            if (!(u[k] >= 0.0 && u[k] < 1.0)) fail(JQ_EINVAL, "jq_sample: draws must lie in [0, 1)");
+        if (count == 0) return;
+        // zero state check from the FP64 norm (the sampler needs a positive total)
+        double nrm = 0.0;
+        {
+            const int none = 0;
+            double p[1];
+            do_probabilities(s, &none, 0, p);
+            nrm = p[0];
+        }
+        if (!(nrm > 0.0)) fail(JQ_EZERO, "jq_sample: zero state");
+        const size_t work = sample_scratch_doubles(s->n);
+        const size_t batch = std::min<size_t>(count, 1u << 20);  // draws per round trip
+        double* scratch = partials(s, work + 2 * batch);
+        double* u_dev = scratch + work;
+        uint64_t* out_dev = reinterpret_cast<uint64_t*>(u_dev + batch);
+        for (size_t first = 0; first < count; first += batch) {
+            const size_t c = std::min(batch, count - first);
+            JQ_HIP(hipMemcpyAsync(u_dev, u + first, c * sizeof(double), hipMemcpyHostToDevice, s->stream));
+            {
+                Timed t(s, K_REDUCE, std::ldexp(1.0, s->n) * (s->enc == JQ_COMPACT ? 1 : bytes_per_amp(s->enc)));
+                if (s->enc == JQ_COMPACT) cp_sample(compact_bufs(s), s->n, u_dev, c, out_dev, scratch, s->stream);
+                else sv_sample(s->enc, s->buf, s->n, u_dev, c, out_dev, scratch, s->stream);
+            }
+            JQ_HIP(hipMemcpyAsync(out + first, out_dev, c * sizeof(uint64_t), hipMemcpyDeviceToHost, s->stream));
+            JQ_HIP(hipStreamSynchronize(s->stream));
+        }
+    });
+}
+
 int jq_project(jq_state* s, int qubit, int value, double* p_out) {
     return guarded([&] {
         check_state(s);

@@ -92,6 +92,7 @@ SIGNATURES = {
     "jq_probabilities": (ctypes.c_int, [_VP, _IP, ctypes.c_int, _DP]),
     "jq_expectations": (ctypes.c_int, [_VP, _DP, _DP, _DP]),
     "jq_renormalize": (ctypes.c_int, [_VP]),
+    "jq_sample": (ctypes.c_int, [_VP, _DP, ctypes.c_size_t, ctypes.POINTER(_U64)]),
     "jq_project": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _DP]),
     "jq_measure": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_double, _IP, _DP]),
     "jq_read_amplitudes": (ctypes.c_int, [_VP, _U64, _U64, _DP]),
@@ -294,6 +295,14 @@ class State:
         """SHORBOX (App. A): 2^(-n_x/2) sum_x |x>|y^x mod G>, x on the low n_x qubits."""
         check(lib().jq_shorbox(self.h, n_x, G, y))
         return self
+
+    def sample(self, u):
+        """Basis states drawn from |a|^2 (App. A, GENERATE EVENTS) for the
+        caller's draws u in [0, 1); returns a uint64 array."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        out = np.zeros(max(1, len(u)), dtype=np.uint64)
+        check(lib().jq_sample(self.h, _dp(u), len(u), out.ctypes.data_as(ctypes.POINTER(_U64))))
+        return out[:len(u)]
 
     def project(self, qubit, value):
         """Project qubit onto |value> and renormalise (App. A, CLEAR / SET);
