@@ -177,6 +177,18 @@ int jq_apply_gate(jq_state *s, int kind, const int *qubits, int nq, const int *c
  * floating-point rounding.  Asynchronous. */
 int jq_apply_circuit(jq_state *s, const jq_gate *gates, size_t count, const jq_exec_opts *opts);
 
+/* jq_apply_circuit with the depolarizing channel of App. A: after each gate
+ * (identity gates included), every qubit q receives an X gate with
+ * probability px, a Y gate with probability py or a Z gate with probability
+ * pz, decided by the caller's draw u[g * N + q] in [0, 1) for gate g: X if
+ * u < px, Y if px <= u < px + py, Z if px + py <= u < px + py + pz, no gate
+ * otherwise.  u holds count * N draws (host; the library draws no random
+ * numbers).  JQ_EINVAL unless px, py, pz >= 0 with px + py + pz <= 1 and
+ * every draw lies in [0, 1); the state is unchanged on error.  The
+ * inserted gates are planned and fused with the circuit.  Asynchronous. */
+int jq_apply_circuit_noisy(jq_state *s, const jq_gate *gates, size_t count, double px, double py, double pz,
+                           const double *u, const jq_exec_opts *opts);
+
 /* The schedule jq_apply_circuit follows for these gates on an N-qubit state
  * of encoding enc with these options (host only: no device work, no state).
  * The planner groups gates into blocks (Sec. 5.2 proposes such fusion); a

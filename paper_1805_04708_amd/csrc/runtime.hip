@@ -557,6 +557,45 @@ int jq_apply_circuit(jq_state* s, const jq_gate* gates, size_t count, const jq_e
     });
 }
 
+int jq_apply_circuit_noisy(jq_state* s, const jq_gate* gates, size_t count, double px, double py, double pz,
+                           const double* u, const jq_exec_opts* opts) {
+    return guarded([&] {
+        check_state(s);
+        if (count && (!gates || !u)) fail(JQ_EINVAL, "jq_apply_circuit_noisy: null array");
+        if (!(px >= 0.0 && py >= 0.0 && pz >= 0.0 && px + py + pz <= 1.0 + 1e-12))
+            fail(JQ_EINVAL, "jq_apply_circuit_noisy: need p_x, p_y, p_z >= 0 with sum <= 1");
+        const int n = s->n;
+        // the channel's Pauli gates (App. A matrices), lowered once per qubit
+        std::vector<GateOp> pauli[3];
+        const char* names[3] = {"X", "Y", "Z"};
+        for (int k = 0; k < 3; ++k)
+            for (int q = 0; q < n; ++q) {
+                jq_gate g;
+                gate_named(names[k], &q, 1, nullptr, 0, &g);
+                pauli[k].push_back(canonicalize(g, n));
+            }
+        std::vector<GateOp> ops;
+        ops.reserve(count * 2);
+        for (size_t i = 0; i < count; ++i) {
+            if (gates[i].nq != 0) {
+                try {
+                    ops.push_back(canonicalize(gates[i], n));
+                } catch (const Error& e) {
+                    fail(e.code, "gate " + std::to_string(i) + ": " + e.what());
+                }
+            }
+            for (int q = 0; q < n; ++q) {
+                const double x = u[i * (size_t)n + q];
+                if (!(x >= 0.0 && x < 1.0)) fail(JQ_EINVAL, "jq_apply_circuit_noisy: draws must lie in [0, 1)");
+                if (x < px) ops.push_back(pauli[0][q]);
+                else if (x < px + py) ops.push_back(pauli[1][q]);
+                else if (x < px + py + pz) ops.push_back(pauli[2][q]);
+            }
+        }
+        apply_ops(s, ops, plan_config(s->n, s->enc, opts));
+    });
+}
+
 int jq_sample(jq_state* s, const double* u, size_t count, uint64_t* out) {
     return guarded([&] {
         check_state(s);

@@ -84,6 +84,8 @@ SIGNATURES = {
     "jq_gate_named": (ctypes.c_int, [ctypes.c_char_p, _IP, ctypes.c_int, _DP, ctypes.c_int, ctypes.POINTER(Gate)]),
     "jq_apply_gate": (ctypes.c_int, [_VP, ctypes.c_int, _IP, ctypes.c_int, _IP, ctypes.c_int, _DP]),
     "jq_apply_circuit": (ctypes.c_int, [_VP, ctypes.POINTER(Gate), ctypes.c_size_t, ctypes.POINTER(ExecOpts)]),
+    "jq_apply_circuit_noisy": (ctypes.c_int, [_VP, ctypes.POINTER(Gate), ctypes.c_size_t, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_double, _DP, ctypes.POINTER(ExecOpts)]),
     "jq_plan_schedule": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Gate), ctypes.c_size_t,
                                         ctypes.POINTER(ExecOpts), ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -269,6 +271,18 @@ class State:
         arr, cnt = circuit if isinstance(circuit, tuple) else gates(circuit)
         opts = exec_opts(fusion, compact_mode, max_ops)
         check(lib().jq_apply_circuit(self.h, arr, cnt, ctypes.byref(opts)))
+        return self
+
+    def apply_circuit_noisy(self, circuit, px, py, pz, u, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0):
+        """apply_circuit with the depolarizing channel (App. A); u holds one
+        draw in [0, 1) per gate and qubit, u[g * N + q]."""
+        arr, cnt = circuit if isinstance(circuit, tuple) else gates(circuit)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        if u.size != cnt * self.n:
+            raise JqError(JQ_EINVAL, "one draw per gate and qubit")
+        opts = exec_opts(fusion, compact_mode, max_ops)
+        check(lib().jq_apply_circuit_noisy(self.h, arr, cnt, px, py, pz, _dp(u if u.size else np.zeros(1)),
+                                           ctypes.byref(opts)))
         return self
 
     def norm(self):
