@@ -216,6 +216,7 @@ def main():
         out["compact"] = compact_extra()
         out["compact_dense"] = compact_dense_extra()
         out["shor"] = shor_extra()
+        out["aux"] = aux_extra()
         out["large_states"] = large_extra()
 
     if args.copy_calibration:
@@ -465,6 +466,27 @@ def shor_extra(n=30, n_x=20, G=1007, y=529):
         out[enc] = {"seconds": dt, "max_dev_from_exact": float(max(np.max(np.abs(qx - ex)), np.max(np.abs(qy - ey)),
                                                                    np.max(np.abs(qz - ez))))}
     return out
+
+
+def aux_extra(n=48, pairs=20, m=64, seed=48):
+    """Auxiliary-variable amplitudes (Sec. 4.2) of a 48-qubit circuit with
+    20 CZ gates (2^20 assignments) for 64 basis states: no state vector."""
+    import numpy as np
+    from paper_1805_04708_amd import jq
+    from paper_1805_04708_amd import workloads as W
+
+    rng = np.random.default_rng(seed)
+    circ = [("H", (q,), ()) for q in range(n)]
+    for p in range(pairs):
+        a, b = (int(x) for x in rng.permutation(n)[:2])
+        circ += [("CZ", (a, b), ()), ("MAT1", (b,), W.haar_u2(rng))]
+    idx = rng.integers(0, 1 << 62, m, dtype=np.uint64) & np.uint64((1 << n) - 1)
+    jq.aux_amplitudes(n, circ, idx[:8])
+    t0 = time.perf_counter()
+    amp = jq.aux_amplitudes(n, circ, idx)
+    dt = time.perf_counter() - t0
+    return {"n": n, "entangling_gates": pairs, "assignments": 2 ** pairs, "amplitudes": m, "gates": len(circ),
+            "seconds": dt, "max_abs_amplitude": float(np.max(np.abs(amp)))}
 
 
 def large_extra():

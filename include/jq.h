@@ -232,6 +232,25 @@ int jq_renormalize(jq_state *s);
  * [0, 1), JQ_EZERO for a zero state.  Synchronises. */
 int jq_sample(jq_state *s, const double *u, size_t count, uint64_t *out);
 
+/* ---- auxiliary-variable amplitudes (Sec. 4.2) ------------------------- */
+
+/* Amplitudes <b|psi> of psi = gates applied to |0...0> on N qubits
+ * (1 <= N <= 63), computed without a state vector by the auxiliary-variable
+ * method of Sec. 4.2 (Eqs. appa2-appa7): every controlled phase shift
+ * (CZ, U(k), CP, a two-qubit diagonal, a singly controlled one-qubit
+ * diagonal) and every CNOT (as H U(pi) H on its target) gets a two-valued
+ * variable; for each of the 2^P assignments the qubits evolve one by one,
+ * and the amplitude is 2^-P times the sum over assignments of the product
+ * of the qubits' components (FP64).  Time O(2^P (G + N M)), memory O(N + M).
+ * Supported: one-qubit gates without controls, X with at most one control,
+ * diagonal gates as listed; anything else (Toffoli, SWAP, MAT2, controlled
+ * dense gates) returns JQ_EUNSUPPORTED, as do more than 40 entangling
+ * gates.  basis[0..m-1] (host) are indices below 2^N; out (host) receives
+ * m interleaved complex values.  Runs on the current HIP device and
+ * allocates its own small buffers.  Synchronises. */
+int jq_aux_amplitudes(int n_qubits, const jq_gate *gates, size_t count, const uint64_t *basis, size_t m,
+                      double *out);
+
 /* ---- projection (App. A: CLEAR, SET, M) ------------------------------- */
 
 /* Project qubit `qubit` onto |value> (value 0: CLEAR, 1: SET) and

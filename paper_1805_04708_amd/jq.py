@@ -94,6 +94,8 @@ SIGNATURES = {
     "jq_probabilities": (ctypes.c_int, [_VP, _IP, ctypes.c_int, _DP]),
     "jq_expectations": (ctypes.c_int, [_VP, _DP, _DP, _DP]),
     "jq_renormalize": (ctypes.c_int, [_VP]),
+    "jq_aux_amplitudes": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Gate), ctypes.c_size_t,
+                                         ctypes.POINTER(_U64), ctypes.c_size_t, _DP]),
     "jq_sample": (ctypes.c_int, [_VP, _DP, ctypes.c_size_t, ctypes.POINTER(_U64)]),
     "jq_project": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _DP]),
     "jq_measure": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_double, _IP, _DP]),
@@ -198,6 +200,18 @@ def plan_schedule(n, enc, circuit, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, m
                                  blen.ctypes.data_as(i32), bfused.ctypes.data_as(i32), ctypes.byref(nb)))
     k = int(blen[:nb.value].sum())
     return order[:k].copy(), blen[:nb.value].copy(), bfused[:nb.value].astype(bool)
+
+
+def aux_amplitudes(n, circuit, basis):
+    """<b|circuit|0...0> for each b in basis by the auxiliary-variable method
+    (Sec. 4.2): no state vector, time exponential only in the number of
+    entangling gates."""
+    arr, cnt = circuit if isinstance(circuit, tuple) else gates(circuit)
+    b = np.ascontiguousarray(basis, dtype=np.uint64)
+    out = np.zeros(max(1, b.size), dtype=np.complex128)
+    check(lib().jq_aux_amplitudes(n, arr, cnt, b.ctypes.data_as(ctypes.POINTER(_U64)), b.size,
+                                  _dp(out.view(np.float64))))
+    return out[:b.size]
 
 
 # -------------------------------------------------------------- state --
