@@ -220,20 +220,24 @@ __global__ __launch_bounds__(kBlock) void k_expect(L ldr, Ins ins, uint64_t qbit
 
 
 template <class L>
-__global__ __launch_bounds__(kBlock) void k_sample_block_sums(L ldr, uint64_t dim, double* __restrict__ bsum) {
+__global__ __launch_bounds__(kBlock) void k_sample_block_sums(L ldr, uint64_t dim, uint64_t nblocks,
+                                                              double* __restrict__ bsum) {
     __shared__ double cs[kBlock];
     ldr.prepare();
-    const uint64_t first = ((uint64_t)blockIdx.x << kSampleBlockBits) + (uint64_t)threadIdx.x * kSampleLeaf;
-    double w = 0.0;
+    for (uint64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+        const uint64_t first = (blk << kSampleBlockBits) + (uint64_t)threadIdx.x * kSampleLeaf;
+        double w = 0.0;
 #pragma unroll
-    for (int k = 0; k < kSampleLeaf; ++k)
-        if (first + k < dim) w = w + ldr.modulus2(first + k);
-    cs[threadIdx.x] = w;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int j = 0; j < kBlock; ++j) t = t + cs[j];
-        bsum[blockIdx.x] = t;
+        for (int k = 0; k < kSampleLeaf; ++k)
+            if (first + k < dim) w = w + ldr.modulus2(first + k);
+        cs[threadIdx.x] = w;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int j = 0; j < kBlock; ++j) t = t + cs[j];
+            bsum[blk] = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -376,7 +380,8 @@ void launch_sample(const L& ldr, int n, const double* u_dev, uint64_t count, uin
     double* bp = bsum + nblocks;
     double* ssum = bp + nblocks;
     double* sp = ssum + nsuper;
-    hipLaunchKernelGGL(k_sample_block_sums<L>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, ldr, dim, bsum);
+    hipLaunchKernelGGL(k_sample_block_sums<L>, dim3((unsigned)(nblocks < (1ull << 20) ? nblocks : (1ull << 20))),
+                       dim3(kBlock), 0, st, ldr, dim, nblocks, bsum);
     hipLaunchKernelGGL(k_sample_block_prefix, dim3(blocks_for(nsuper, 64)), dim3(64), 0, st, bsum, nblocks, nsuper,
                        bp, ssum);
     hipLaunchKernelGGL(k_sample_super_prefix, dim3(1), dim3(64), 0, st, ssum, nsuper, sp);

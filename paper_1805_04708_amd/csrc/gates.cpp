@@ -300,4 +300,15 @@ GateOp canonicalize(const jq_gate& g, int n) {
     return op;
 }
 
+bool phase_code_shifts(const GateOp& op, double d[4]) {
+    constexpr double kPi = 3.14159265358979323846;
+    bool clear = true;
+    for (int i = 0; i < 4; ++i) {
+        d[i] = (128.0 * std::atan2(op.m[i].im, op.m[i].re)) / kPi;
+        const double f = d[i] - std::floor(d[i]);
+        clear = clear && !(std::fabs(f - 0.5) < 1e-6);
+    }
+    return clear;
+}
+
 }  // namespace jq

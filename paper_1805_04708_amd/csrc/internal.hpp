@@ -69,6 +69,12 @@ struct GateOp {
 // Lower a jq_gate (ABI form) to a canonical op, validating it against n.
 GateOp canonicalize(const jq_gate& g, int n);
 
+// Phase-code shifts of a modulus-preserving diagonal op on the two-byte code:
+// d[i] = 128 arg(m[i]) / pi in code units.  False when a shift lies within
+// 1e-6 of a half-integer (a rounding tie, which the amplitude's own value
+// must decide); then the op is applied by decoding, rotating and encoding.
+bool phase_code_shifts(const GateOp& op, double d[4]);
+
 // Lower a named App. A instruction into a jq_gate (throws Error).
 int gate_named(const char* name, const int* qubits, int nq, const double* params, int np, jq_gate* out);
 
@@ -90,6 +96,7 @@ enum FOpKind : int32_t {
     F_DIAG = 8,         // diagonal with one or two selector bits
     F_MDENSE_REG = 9,   // 2x2 on a register slot chosen by 1-2 selector bits
     F_MDENSE_LANE = 10, // 2x2 on a lane bit chosen by 1-2 selector bits
+    F_CSHIFT = 11,      // two-byte code: add the integer m[v] to the phase code (v = selector value)
 };
 
 struct FOp {
@@ -137,6 +144,10 @@ struct PlanConfig {
     int max_ops = 48;
     bool fuse = true;
     bool absorb = true;  // fold diagonal gates into neighbouring dense gates
+    // two-byte code with per-gate quantisation: only permutations and
+    // modulus-preserving phase shifts (exact on the codes) fuse, and no gate
+    // moves past one that does not
+    bool code_domain = false;
 };
 
 struct Plan {
@@ -206,6 +217,9 @@ void cp_shorbox(const CompactBufs& b, int n, int n_x, uint64_t G, uint64_t y, hi
 // lane bits of the compact fused pass fixed to index bits 0..F-1 (each
 // code plane is read in runs of 2^F bytes)
 constexpr int kCpFixedLaneBits = 6;
+// a fused pass of code-domain ops (permutations, integer phase-code shifts)
+// on both code planes, no decoding
+void cp_apply_codes(const CompactBufs& b, int n, const FPass& pass, int k_reg, hipStream_t st);
 // one fused pass quantised once: decode, the pass's ops in FP64, range
 // (unless every gate of the block keeps all moduli), encode
 void cp_apply_block(const CompactBufs& b, int n, const FPass& pass, int k_reg, int fixed_lane_bits,

@@ -669,6 +669,175 @@ __global__ __launch_bounds__(kBlock) void k_cp_shorbox(int8_t* __restrict__ b0, 
     }
 }
 
+// ------------------------------------------------ fused code pass --
+//
+// With per-gate quantisation a permutation swaps code pairs and a
+// modulus-preserving phase shift adds an integer to the phase code of each
+// touched non-zero amplitude (the per-gate kernels above); both are exact
+// on the codes, so a run of them executes as one tile pass over both planes
+// without decoding, with the codes they would produce one by one.  A lane
+// holds 2^K (b0, b1) pairs packed in 32-bit registers (b0 in bits 0-7, b1 in
+// bits 8 and up, reduced mod 256 at the store); lane bits are index bits
+// 0..5, so each plane is read and written in runs of 64 bytes.
+
+template <int K, int J>
+__device__ __forceinline__ void code_perm_reg(uint32_t (&c)[1 << K], uint32_t rc, bool thr_ok) {
+    if constexpr (J < K) {
+#pragma unroll
+        for (int s = 0; s < (1 << K); ++s) {
+            if (s & (1 << J)) continue;
+            const int t = s | (1 << J);
+            const bool ok = thr_ok && ((uint32_t)s & rc) == rc;
+            const uint32_t x = c[s], y = c[t];
+            c[s] = ok ? y : x;
+            c[t] = ok ? x : y;
+        }
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void code_perm_lane(uint32_t (&c)[1 << K], int b, uint32_t rc, bool thr_ok) {
+    const int mask = 1 << b;
+#pragma unroll
+    for (int s = 0; s < (1 << K); ++s) {
+        const uint32_t partner = (uint32_t)__shfl_xor((int)c[s], mask, 64);
+        const bool ok = thr_ok && ((uint32_t)s & rc) == rc;
+        c[s] = ok ? partner : c[s];
+    }
+}
+
+// Phase shifts add into bits 8.. of the packed register: the carry out of
+// the phase byte lands in bits 16.. and is dropped when the codes are stored,
+// so the sum is taken mod 256 as one shift after another would be, and a
+// pending sum travels with its amplitude through later permutations.  The
+// rule that zero amplitudes (b0 = -128) keep phase code 0 is applied at the
+// store (every stored state has phase code 0 on its zero amplitudes).
+// R0: register slot of the selector, or -1 when the shift is the same for
+// all slots of the thread (no selector, or one held by the thread).
+template <int K, int R0>
+__device__ __forceinline__ void code_shift_t(uint32_t (&c)[1 << K], uint32_t d0, uint32_t d1, uint32_t rc,
+                                             bool thr_ok) {
+    const uint32_t e0 = thr_ok ? d0 : 0u, e1 = thr_ok ? d1 : 0u;
+    if (rc == 0) {
+#pragma unroll
+        for (int s = 0; s < (1 << K); ++s) c[s] += (R0 >= 0 && ((s >> R0) & 1)) ? e1 : e0;
+    } else {
+#pragma unroll
+        for (int s = 0; s < (1 << K); ++s) {
+            const uint32_t e = (R0 >= 0 && ((s >> R0) & 1)) ? e1 : e0;
+            c[s] += ((uint32_t)s & rc) == rc ? e : 0u;
+        }
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void code_shift(uint32_t (&c)[1 << K], const FOp* op, uint64_t base, bool thr_ok) {
+    const uint32_t rc = op->reg_ctrl;
+    const int nsel = op->nsel;
+    uint32_t sh[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sh[i] = (uint32_t)(int)op->m[i] << 8;
+    const int g0 = op->sel_glob[0] >= 0 ? (int)((base >> op->sel_glob[0]) & 1) : 0;
+    if (nsel == 0) {
+        code_shift_t<K, -1>(c, sh[0], sh[0], rc, thr_ok);
+    } else if (nsel == 1 && op->sel_reg[0] < 0) {
+        const uint32_t d = g0 ? sh[1] : sh[0];
+        code_shift_t<K, -1>(c, d, d, rc, thr_ok);
+    } else if (nsel == 1) {
+        // one case per selector slot, each closed by its own empty asm
+        // statement (see code_perm_reg_dispatch)
+        switch (op->sel_reg[0]) {
+            case 0: code_shift_t<K, 0>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 0"); break;
+            case 1: code_shift_t<K, 1>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 1"); break;
+            case 2: code_shift_t<K, 2>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 2"); break;
+            case 3: code_shift_t<K, 3>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 3"); break;
+            case 4: code_shift_t<K, 4>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 4"); break;
+            case 5: code_shift_t<K, 5>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 5"); break;
+            case 6: code_shift_t<K, 6>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 6"); break;
+            default: break;
+        }
+    } else {
+        // two selectors (a general two-qubit diagonal): per slot
+        const int g1 = op->sel_glob[1] >= 0 ? (int)((base >> op->sel_glob[1]) & 1) : 0;
+        const int r0 = op->sel_reg[0], r1 = op->sel_reg[1];
+#pragma unroll
+        for (int s = 0; s < (1 << K); ++s) {
+            const int v = 2 * (r0 >= 0 ? (s >> r0) & 1 : g0) + (r1 >= 0 ? (s >> r1) & 1 : g1);
+            uint32_t d = sh[0];
+            d = v == 1 ? sh[1] : d;
+            d = v == 2 ? sh[2] : d;
+            d = v == 3 ? sh[3] : d;
+            const bool ok = thr_ok && ((uint32_t)s & rc) == rc;
+            c[s] += ok ? d : 0u;
+        }
+    }
+}
+
+// Each case ends in its own empty asm statement so that the compiler cannot
+// merge the cases into one body with a run-time register index (which would
+// move the register tile to scratch memory).
+template <int K>
+__device__ __forceinline__ void code_perm_reg_dispatch(uint32_t (&c)[1 << K], int j, uint32_t rc, bool thr_ok) {
+    switch (j) {
+        case 0: code_perm_reg<K, 0>(c, rc, thr_ok); asm volatile("; code slot 0"); break;
+        case 1: code_perm_reg<K, 1>(c, rc, thr_ok); asm volatile("; code slot 1"); break;
+        case 2: code_perm_reg<K, 2>(c, rc, thr_ok); asm volatile("; code slot 2"); break;
+        case 3: code_perm_reg<K, 3>(c, rc, thr_ok); asm volatile("; code slot 3"); break;
+        case 4: code_perm_reg<K, 4>(c, rc, thr_ok); asm volatile("; code slot 4"); break;
+        case 5: code_perm_reg<K, 5>(c, rc, thr_ok); asm volatile("; code slot 5"); break;
+        case 6: code_perm_reg<K, 6>(c, rc, thr_ok); asm volatile("; code slot 6"); break;
+        default: break;
+    }
+}
+
+// Waves loop over the tiles (a launch holds at most 2^32 threads).
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_cp_codes(int8_t* __restrict__ b0, int8_t* __restrict__ b1, FPass P,
+                                                      const FOp* __restrict__ ops, uint64_t ntiles) {
+    constexpr int S = 1 << K;
+    const int lane = threadIdx.x & 63;
+    const uint64_t wpb = blockDim.x >> 6;
+    const uint64_t wave0 = (uint64_t)blockIdx.x * wpb + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * wpb;
+    uint64_t stride[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) stride[j] = 1ull << P.reg_q[j];
+    for (uint64_t w = wave0; w < ntiles; w += nwaves) {
+    const uint64_t base = tile_base(P, w, (uint64_t)lane);
+    uint32_t c[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        uint64_t off = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (s & (1 << j)) off += stride[j];
+        c[s] = (uint32_t)(uint8_t)b0[base + off] | ((uint32_t)(uint8_t)b1[base + off] << 8);
+    }
+    for (int k = 0; k < P.n_ops; ++k) {
+        const FOp* op = ops + k;
+        const bool thr_ok = (base & op->thr_ctrl) == op->thr_ctrl;
+        switch (op->kind) {
+            case F_PERM_REG: code_perm_reg_dispatch<K>(c, op->slot, op->reg_ctrl, thr_ok); break;
+            case F_PERM_LANE: code_perm_lane<K>(c, op->slot, op->reg_ctrl, thr_ok); break;
+            case F_CSHIFT: code_shift<K>(c, op, base, thr_ok); break;
+            default: break;
+        }
+    }
+    uint64_t sbase = base;
+    asm volatile("" : "+v"(sbase));
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        uint64_t off = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (s & (1 << j)) off += stride[j];
+        const uint32_t lo = c[s] & 0xffu;
+        b0[sbase + off] = (int8_t)lo;
+        b1[sbase + off] = (int8_t)(lo == 0x80u ? 0u : (c[s] >> 8) & 0xffu);
+    }
+    }
+}
+
 // ------------------------------------------------------------ launchers --
 
 namespace {
@@ -769,13 +938,7 @@ void cp_apply_op(const CompactBufs& b, int n, const GateOp& op, hipStream_t st) 
         const uint64_t ng = 1ull << (n - __builtin_popcountll(op.cmask));
         const Ins ins = make_ins(op.cmask, op.cmask);
         Shift sh{};
-        bool near_tie = false;
-        for (int i = 0; i < 4; ++i) {
-            sh.d[i] = (128.0 * std::atan2(op.m[i].im, op.m[i].re)) / kPiD;
-            const double f = sh.d[i] - std::floor(sh.d[i]);
-            near_tie |= std::fabs(f - 0.5) < 1e-6;
-        }
-        if (near_tie) {
+        if (!phase_code_shifts(op, sh.d)) {
             // the shift puts every code on a rounding tie: decode, rotate and
             // re-encode each amplitude so the tie is broken by its own value
             hipLaunchKernelGGL(k_cp_phase, dim3(persistent_blocks(ng)), dim3(kBlock), 0, st, b0, b1, ng, ins,
@@ -892,6 +1055,36 @@ void launch_cp_fused(const CompactBufs& b, int n, const FPass& pass, bool keeps,
 }
 
 }  // namespace
+
+namespace {
+
+template <int K>
+void launch_cp_codes(const CompactBufs& b, int n, const FPass& pass, hipStream_t st) {
+    const uint64_t dim = 1ull << n;
+    const uint64_t ntiles = 1ull << (n - 6 - K);
+    const unsigned wpb = (unsigned)(ntiles < 4 ? ntiles : 4);
+    const uint64_t need = ntiles / wpb;
+    // up to 2^20 blocks of 4 waves; larger states loop over their tiles
+    const unsigned blocks = (unsigned)(need < (1ull << 20) ? need : (1ull << 20));
+    hipLaunchKernelGGL((k_cp_codes<K>), dim3(blocks), dim3(64 * wpb), 0, st, b.codes, b.codes + dim, pass, pass.ops,
+                       ntiles);
+    JQ_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void cp_apply_codes(const CompactBufs& b, int n, const FPass& pass, int k_reg, hipStream_t st) {
+    if (n < 6 + k_reg) fail(JQ_EINVAL, "compact code pass: state smaller than a tile");
+    switch (k_reg) {
+        case 2: launch_cp_codes<2>(b, n, pass, st); break;
+        case 3: launch_cp_codes<3>(b, n, pass, st); break;
+        case 4: launch_cp_codes<4>(b, n, pass, st); break;
+        case 5: launch_cp_codes<5>(b, n, pass, st); break;
+        case 6: launch_cp_codes<6>(b, n, pass, st); break;
+        case 7: launch_cp_codes<7>(b, n, pass, st); break;
+        default: fail(JQ_EINVAL, "compact code pass: register bits must be 2..7");
+    }
+}
 
 void cp_apply_block(const CompactBufs& b, int n, const FPass& pass, int k_reg, int fixed_lane_bits, bool keeps,
                     hipStream_t st) {

@@ -14,28 +14,33 @@
 namespace jq {
 
 // ------------------------------------------------------------ per gate --
+//
+// Blocks take chunks of IT * 256 groups (two-qubit: 2 * 256) and loop over
+// chunks when the grid is capped (a launch holds at most 2^32 threads).
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_dense1(typename Vec<R>::T* __restrict__ psi, uint64_t ngroups,
                                                     Ins ins, uint64_t tbit, M4<R> m) {
-    const uint64_t g0 = (uint64_t)blockIdx.x * (kIt * kBlock) + threadIdx.x;
-    uint64_t i0[kIt];
-    Cx<R> a[kIt], b[kIt];
+    for (uint64_t chunk = blockIdx.x; chunk * (kIt * kBlock) < ngroups; chunk += gridDim.x) {
+        const uint64_t g0 = chunk * (kIt * kBlock) + threadIdx.x;
+        uint64_t i0[kIt];
+        Cx<R> a[kIt], b[kIt];
 #pragma unroll
-    for (int u = 0; u < kIt; ++u) {
-        const uint64_t g = g0 + (uint64_t)u * kBlock;
-        if (g < ngroups) {
-            i0[u] = expand(g, ins);
-            a[u] = ld<R>(psi, i0[u]);
-            b[u] = ld<R>(psi, i0[u] | tbit);
+        for (int u = 0; u < kIt; ++u) {
+            const uint64_t g = g0 + (uint64_t)u * kBlock;
+            if (g < ngroups) {
+                i0[u] = expand(g, ins);
+                a[u] = ld<R>(psi, i0[u]);
+                b[u] = ld<R>(psi, i0[u] | tbit);
+            }
         }
-    }
 #pragma unroll
-    for (int u = 0; u < kIt; ++u) {
-        const uint64_t g = g0 + (uint64_t)u * kBlock;
-        if (g < ngroups) {
-            st<R>(psi, i0[u], mac2(m.e[0], a[u], m.e[1], b[u]));
-            st<R>(psi, i0[u] | tbit, mac2(m.e[2], a[u], m.e[3], b[u]));
+        for (int u = 0; u < kIt; ++u) {
+            const uint64_t g = g0 + (uint64_t)u * kBlock;
+            if (g < ngroups) {
+                st<R>(psi, i0[u], mac2(m.e[0], a[u], m.e[1], b[u]));
+                st<R>(psi, i0[u] | tbit, mac2(m.e[2], a[u], m.e[3], b[u]));
+            }
         }
     }
 }
@@ -43,22 +48,24 @@ __global__ __launch_bounds__(kBlock) void k_dense1(typename Vec<R>::T* __restric
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_dense2(typename Vec<R>::T* __restrict__ psi, uint64_t ngroups,
                                                     Ins ins, uint64_t hbit, uint64_t lbit, M16<R> m) {
-    const uint64_t g0 = (uint64_t)blockIdx.x * (2 * kBlock) + threadIdx.x;
+    for (uint64_t chunk = blockIdx.x; chunk * (2 * kBlock) < ngroups; chunk += gridDim.x) {
+        const uint64_t g0 = chunk * (2 * kBlock) + threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const uint64_t g = g0 + (uint64_t)u * kBlock;
-        if (g >= ngroups) continue;
-        const uint64_t i = expand(g, ins);
-        const uint64_t idx[4] = {i, i | lbit, i | hbit, i | hbit | lbit};
-        Cx<R> x[4];
+        for (int u = 0; u < 2; ++u) {
+            const uint64_t g = g0 + (uint64_t)u * kBlock;
+            if (g >= ngroups) continue;
+            const uint64_t i = expand(g, ins);
+            const uint64_t idx[4] = {i, i | lbit, i | hbit, i | hbit | lbit};
+            Cx<R> x[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) x[c] = ld<R>(psi, idx[c]);
+            for (int c = 0; c < 4; ++c) x[c] = ld<R>(psi, idx[c]);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            Cx<R> s = cmul(m.e[4 * r], x[0]);
+            for (int r = 0; r < 4; ++r) {
+                Cx<R> s = cmul(m.e[4 * r], x[0]);
 #pragma unroll
-            for (int c = 1; c < 4; ++c) s = cadd(s, cmul(m.e[4 * r + c], x[c]));
-            st<R>(psi, idx[r], s);
+                for (int c = 1; c < 4; ++c) s = cadd(s, cmul(m.e[4 * r + c], x[c]));
+                st<R>(psi, idx[r], s);
+            }
         }
     }
 }
@@ -66,44 +73,48 @@ __global__ __launch_bounds__(kBlock) void k_dense2(typename Vec<R>::T* __restric
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_diag(typename Vec<R>::T* __restrict__ psi, uint64_t ngroups,
                                                   Ins ins, int nsel, int s0, int s1, M4<R> d) {
-    const uint64_t g0 = (uint64_t)blockIdx.x * (kIt * kBlock) + threadIdx.x;
+    for (uint64_t chunk = blockIdx.x; chunk * (kIt * kBlock) < ngroups; chunk += gridDim.x) {
+        const uint64_t g0 = chunk * (kIt * kBlock) + threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < kIt; ++u) {
-        const uint64_t g = g0 + (uint64_t)u * kBlock;
-        if (g >= ngroups) continue;
-        const uint64_t i = expand(g, ins);
-        int sel = 0;
-        if (nsel >= 1) sel = (int)((i >> s0) & 1);
-        if (nsel == 2) sel = 2 * sel + (int)((i >> s1) & 1);
-        Cx<R> f = d.e[0];
-        f = csel(sel == 1, d.e[1], f);
-        f = csel(sel == 2, d.e[2], f);
-        f = csel(sel == 3, d.e[3], f);
-        st<R>(psi, i, cmul(f, ld<R>(psi, i)));
+        for (int u = 0; u < kIt; ++u) {
+            const uint64_t g = g0 + (uint64_t)u * kBlock;
+            if (g >= ngroups) continue;
+            const uint64_t i = expand(g, ins);
+            int sel = 0;
+            if (nsel >= 1) sel = (int)((i >> s0) & 1);
+            if (nsel == 2) sel = 2 * sel + (int)((i >> s1) & 1);
+            Cx<R> f = d.e[0];
+            f = csel(sel == 1, d.e[1], f);
+            f = csel(sel == 2, d.e[2], f);
+            f = csel(sel == 3, d.e[3], f);
+            st<R>(psi, i, cmul(f, ld<R>(psi, i)));
+        }
     }
 }
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_permx(typename Vec<R>::T* __restrict__ psi, uint64_t ngroups,
                                                    Ins ins, uint64_t tbit) {
-    const uint64_t g0 = (uint64_t)blockIdx.x * (kIt * kBlock) + threadIdx.x;
-    uint64_t i0[kIt];
-    Cx<R> a[kIt], b[kIt];
+    for (uint64_t chunk = blockIdx.x; chunk * (kIt * kBlock) < ngroups; chunk += gridDim.x) {
+        const uint64_t g0 = chunk * (kIt * kBlock) + threadIdx.x;
+        uint64_t i0[kIt];
+        Cx<R> a[kIt], b[kIt];
 #pragma unroll
-    for (int u = 0; u < kIt; ++u) {
-        const uint64_t g = g0 + (uint64_t)u * kBlock;
-        if (g < ngroups) {
-            i0[u] = expand(g, ins);
-            a[u] = ld<R>(psi, i0[u]);
-            b[u] = ld<R>(psi, i0[u] | tbit);
+        for (int u = 0; u < kIt; ++u) {
+            const uint64_t g = g0 + (uint64_t)u * kBlock;
+            if (g < ngroups) {
+                i0[u] = expand(g, ins);
+                a[u] = ld<R>(psi, i0[u]);
+                b[u] = ld<R>(psi, i0[u] | tbit);
+            }
         }
-    }
 #pragma unroll
-    for (int u = 0; u < kIt; ++u) {
-        const uint64_t g = g0 + (uint64_t)u * kBlock;
-        if (g < ngroups) {
-            st<R>(psi, i0[u], b[u]);
-            st<R>(psi, i0[u] | tbit, a[u]);
+        for (int u = 0; u < kIt; ++u) {
+            const uint64_t g = g0 + (uint64_t)u * kBlock;
+            if (g < ngroups) {
+                st<R>(psi, i0[u], b[u]);
+                st<R>(psi, i0[u] | tbit, a[u]);
+            }
         }
     }
 }
@@ -302,6 +313,12 @@ Ins make_ins(uint64_t zero_bits, uint64_t ones) {
     return s;
 }
 
+// blocks for a per-gate kernel whose blocks loop over chunks of per_block
+unsigned chunk_blocks(uint64_t items, uint64_t per_block) {
+    const uint64_t b = (items + per_block - 1) / per_block;
+    return (unsigned)(b < 1 ? 1 : b < (1ull << 22) ? b : (1ull << 22));
+}
+
 unsigned blocks_for(uint64_t items, uint64_t per_block) {
     uint64_t b = (items + per_block - 1) / per_block;
     if (b == 0) b = 1;
@@ -325,7 +342,7 @@ void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, hipStream_t st
             const uint64_t ng = 1ull << (n - 1 - fixed);
             M4<R> m;
             for (int i = 0; i < 4; ++i) m.e[i] = {(R)op.m[i].re, (R)op.m[i].im};
-            hipLaunchKernelGGL(k_dense1<R>, dim3(blocks_for(ng, kIt * kBlock)), dim3(kBlock), 0, st, psi, ng,
+            hipLaunchKernelGGL(k_dense1<R>, dim3(chunk_blocks(ng, kIt * kBlock)), dim3(kBlock), 0, st, psi, ng,
                                make_ins(op.cmask | tb, op.cmask), tb, m);
             break;
         }
@@ -334,7 +351,7 @@ void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, hipStream_t st
             const uint64_t ng = 1ull << (n - 2 - fixed);
             M16<R> m;
             for (int i = 0; i < 16; ++i) m.e[i] = {(R)op.m[i].re, (R)op.m[i].im};
-            hipLaunchKernelGGL(k_dense2<R>, dim3(blocks_for(ng, 2 * kBlock)), dim3(kBlock), 0, st, psi, ng,
+            hipLaunchKernelGGL(k_dense2<R>, dim3(chunk_blocks(ng, 2 * kBlock)), dim3(kBlock), 0, st, psi, ng,
                                make_ins(op.cmask | hb | lb, op.cmask), hb, lb, m);
             break;
         }
@@ -342,7 +359,7 @@ void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, hipStream_t st
             const uint64_t ng = 1ull << (n - fixed);
             M4<R> d;
             for (int i = 0; i < 4; ++i) d.e[i] = {(R)op.m[i].re, (R)op.m[i].im};
-            hipLaunchKernelGGL(k_diag<R>, dim3(blocks_for(ng, kIt * kBlock)), dim3(kBlock), 0, st, psi, ng,
+            hipLaunchKernelGGL(k_diag<R>, dim3(chunk_blocks(ng, kIt * kBlock)), dim3(kBlock), 0, st, psi, ng,
                                make_ins(op.cmask, op.cmask), op.nsel, op.t0 < 0 ? 0 : op.t0,
                                op.t1 < 0 ? 0 : op.t1, d);
             break;
@@ -350,7 +367,7 @@ void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, hipStream_t st
         case OP_PERMX: {
             const uint64_t tb = 1ull << op.t0;
             const uint64_t ng = 1ull << (n - 1 - fixed);
-            hipLaunchKernelGGL(k_permx<R>, dim3(blocks_for(ng, kIt * kBlock)), dim3(kBlock), 0, st, psi, ng,
+            hipLaunchKernelGGL(k_permx<R>, dim3(chunk_blocks(ng, kIt * kBlock)), dim3(kBlock), 0, st, psi, ng,
                                make_ins(op.cmask | tb, op.cmask), tb);
             break;
         }
@@ -364,6 +381,7 @@ template <typename R, int K, int F>
 void launch_fused(typename Vec<R>::T* psi, int n, const FPass& p, hipStream_t st) {
     const uint64_t waves = 1ull << (n - 6 - K);
     const uint64_t wpb = waves < 4 ? waves : 4;
+    if (waves >= (1ull << 26)) fail(JQ_EUNSUPPORTED, "fused pass: too many tiles for one launch (use more register qubits)");
     hipLaunchKernelGGL((k_fused<R, K, F>), dim3(blocks_for(waves, wpb)), dim3(64 * wpb), 0, st, psi, p, p.ops);
     JQ_HIP(hipGetLastError());
 }

@@ -48,8 +48,29 @@ double touched_fraction(const GateOp& op, int n) {
     return std::ldexp((double)op.touched(n), -n);
 }
 
+// Can the op run inside a fused pass?  Two-qubit dense ops never do; on the
+// two-byte code with per-gate quantisation only the ops that are exact on
+// the codes do: permutations and phase shifts by a non-tie integer.
+bool fusable(const GateOp& op, const PlanConfig& cfg) {
+    if (op.kind == OP_DENSE2) return false;
+    if (!cfg.code_domain) return true;
+    if (op.kind == OP_PERMX) return true;
+    double d[4];
+    return op.kind == OP_DIAG && op.keeps_modulus && phase_code_shifts(op, d);
+}
+
+// Bytes the op moves as a per-gate kernel, in units of one fused pass
+// (state vector: the touched amplitudes read and written; two-byte code: a
+// permutation reads and writes both planes of the touched amplitudes, a phase
+// shift reads the modulus plane and reads and writes the phase plane).
+double single_cost(const GateOp& op, const PlanConfig& cfg) {
+    const double t = touched_fraction(op, cfg.n);
+    if (!cfg.code_domain) return t;
+    return op.kind == OP_PERMX ? t : 0.75 * t;
+}
+
 FOp lower_fop(const GateOp& op, const FPass& p, int F, int K, int nmux = 0, const int* mux = nullptr,
-              const cd (*mats)[4] = nullptr) {
+              const cd (*mats)[4] = nullptr, bool code_domain = false) {
     FOp f{};
     auto reg_of = [&](int q) {
         for (int j = 0; j < K; j++) if (p.reg_q[j] == q) return j;
@@ -98,6 +119,21 @@ FOp lower_fop(const GateOp& op, const FPass& p, int F, int K, int nmux = 0, cons
                     f.m[8 * v + 2 * i + 1] = mats[v][i].im;
                 }
         }
+        return f;
+    }
+    if (op.kind == OP_DIAG && code_domain) {
+        // integer phase-code shift per selector value (rint of a non-tie shift)
+        f.kind = F_CSHIFT;
+        f.nsel = op.nsel;
+        int sel[2] = {op.t0, op.t1};
+        for (int i = 0; i < op.nsel; i++) {
+            int j = reg_of(sel[i]);
+            if (j >= 0) f.sel_reg[i] = j;
+            else f.sel_glob[i] = sel[i];
+        }
+        double d[4];
+        phase_code_shifts(op, d);
+        for (int i = 0; i < 4; i++) f.m[i] = std::rint(d[i]);
         return f;
     }
     if (op.kind == OP_DIAG) {
@@ -305,12 +341,15 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
             const GateOp& op = ops[remaining[r]];
             const uint64_t sup = op.support();
             const bool diag = op.kind == OP_DIAG;
+            // on the two-byte code with per-gate quantisation no gate may move
+            // past one that decodes: the scan ends there
+            if (cfg.code_domain && !fusable(op, cfg)) break;
             if ((sup & blk_any) || (!diag && (sup & blk_diag))) {
                 (diag ? blk_diag : blk_any) |= sup;
                 continue;
             }
             bool ok = true;
-            if (op.kind == OP_DENSE2) {
+            if (!fusable(op, cfg)) {
                 ok = false;  // two-qubit dense blocks run unfused
             } else if (!diag) {
                 PassBuilder trial = pb;
@@ -336,7 +375,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
         }
         // emit singles when they move fewer bytes than one full pass
         double singles = 0;
-        for (int i : pb.taken) singles += touched_fraction(ops[i], n);
+        for (int i : pb.taken) singles += single_cost(ops[i], cfg);
         std::vector<char> is_taken(ops.size(), 0);
         for (int i : pb.taken) is_taken[i] = 1;
         std::vector<int> rest;
@@ -393,7 +432,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
             // a diagonal on the target alone folds into the matrix itself
             if (po.op.kind == OP_DENSE1 && po.nsel == 0)
                 for (int e = 0; e < 4; ++e) po.op.m[e] = po.mats[0][e];
-            plan.fops.push_back(lower_fop(po.op, p, F, K, po.nsel, po.sel, po.mats));
+            plan.fops.push_back(lower_fop(po.op, p, F, K, po.nsel, po.sel, po.mats, cfg.code_domain));
             ++n_ops;
         }
         p.n_ops = n_ops;

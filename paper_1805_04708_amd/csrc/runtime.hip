@@ -57,10 +57,11 @@ int guarded(F&& f) {
 // ------------------------------------------------------ kernel timing --
 
 enum KClass {
-    K_DENSE1, K_DENSE2, K_DIAG, K_PERMX, K_FUSED, K_CP_GATE, K_CP_PERM, K_CP_PHASE, K_REDUCE, K_CP_FUSED, K_NCLASS
+    K_DENSE1, K_DENSE2, K_DIAG, K_PERMX, K_FUSED, K_CP_GATE, K_CP_PERM, K_CP_PHASE, K_REDUCE, K_CP_FUSED,
+    K_CP_CODES, K_NCLASS
 };
 const char* kClassName[K_NCLASS] = {"dense1", "dense2", "diag", "permx", "fused", "compact_gate",
-                                    "compact_perm", "compact_phase", "reduce", "compact_fused"};
+                                    "compact_perm", "compact_phase", "reduce", "compact_fused", "compact_codes"};
 
 struct Timed {
     jq_state* s;
@@ -181,14 +182,20 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
     c.k_reg = compact ? 4 : enc == JQ_C64 ? 5 : 4;
     const int k_max = compact ? 4 : enc == JQ_C64 ? 6 : 5;
     c.max_ops = 48;
-    c.fuse = !compact;
+    c.fuse = true;
+    // two-byte code, per-gate quantisation (the default): code-domain passes
+    c.code_domain = compact;
     if (opts) {
         if (opts->compact_mode != JQ_COMPACT_PER_GATE && opts->compact_mode != JQ_COMPACT_PER_BLOCK)
             fail(JQ_EINVAL, "jq_exec_opts: bad compact_mode");
-        if (compact && opts->compact_mode == JQ_COMPACT_PER_BLOCK) c.fuse = true;
+        if (compact && opts->compact_mode == JQ_COMPACT_PER_BLOCK) c.code_domain = false;
         if (opts->fusion == 1) c.fuse = false;
-        else if (opts->fusion >= 2) c.k_reg = std::min(opts->fusion, k_max);
+        else if (opts->fusion >= 2) c.k_reg = std::min(opts->fusion, c.code_domain ? 7 : k_max);
         if (opts->max_ops > 0) c.max_ops = std::min(opts->max_ops, 256);
+    }
+    if (c.code_domain) {
+        c.absorb = false;
+        if (!(opts && opts->fusion >= 2)) c.k_reg = 5;
     }
     while (c.fuse && c.k_reg > 2 && c.n < 6 + c.k_reg) c.k_reg--;
     return c;
@@ -241,6 +248,11 @@ void apply_ops(jq_state* s, const std::vector<GateOp>& ops, const PlanConfig& cf
         }
         FPass p = step.pass;
         p.ops = dev + step.first_fop;
+        if (s->enc == JQ_COMPACT && cfg.code_domain) {
+            Timed t(s, K_CP_CODES, 2.0 * sweep);
+            cp_apply_codes(compact_bufs(s), s->n, p, step.k_reg, s->stream);
+            continue;
+        }
         if (s->enc == JQ_COMPACT) {
             bool keeps = true;
             for (int g : step.gates) keeps = keeps && ops[g].keeps_modulus;

@@ -123,3 +123,28 @@ def test_n37_two_byte_code_ghz_and_phases():
         b0, b1, rng = s.codes(0, 1 << 12)
         assert np.all(b0 == -127) and abs(rng[0] - 2.0 ** (-n / 2)) < 1e-30
         assert abs(s.norm() - 1.0) < 1e-13
+        # sampling at 2^37 amplitudes (the block sums loop over their blocks):
+        # every probability is the same rounded value of 2^-37, so the event
+        # is floor(u 2^37) up to the rounding of the cumulative sums
+        u = np.random.default_rng(37).random(4096)
+        got = s.sample(u).astype(np.int64)
+        assert np.max(np.abs(got - np.floor(u * 2.0 ** n).astype(np.int64))) <= 1
+
+
+def test_n34_per_gate_kernels_on_the_full_grid():
+    # unfused gates at 2^34 amplitudes: the per-gate kernels loop over chunks
+    # of a capped grid (a launch holds at most 2^32 threads)
+    n = 34
+    if free_gib() < 257:
+        pytest.skip("needs 256 GiB of free HBM")
+    with jq.State(n, "c128") as s:
+        s.init(jq.JQ_INIT_UNIFORM)
+        theta = 0.8
+        s.apply_circuit([("RZ", (5,), (theta,)), ("CNOT", (3, 33), ()), ("H", (7,), ())], fusion=1)
+        amp = 2.0 ** (-n / 2)
+        for i in [0, 1 << 5, (1 << n) - 1, 987654321]:
+            # H on qubit 7 of a uniform state: sqrt(2) amp on bit 7 = 0, 0 on bit 7 = 1
+            want = 0.0 if (i >> 7) & 1 else math.sqrt(2) * amp
+            want *= np.exp(-0.5j * theta) if not (i >> 5) & 1 else np.exp(0.5j * theta)
+            assert abs(s.amplitudes(i, 1)[0] - want) < 1e-15, i
+        assert abs(s.norm() - 1.0) < 1e-12

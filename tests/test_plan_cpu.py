@@ -3,6 +3,8 @@ together in one tile pass and in which order.  These checks need no GPU:
 the order must be a permutation of the circuit that the oracle maps to the
 same state (gates only move past gates they commute with), every fused
 block must fit one tile, and the options select the documented modes."""
+import math
+
 import numpy as np
 import pytest
 
@@ -87,7 +89,7 @@ def test_fused_blocks_fit_one_tile(enc, kw):
 def test_unfused_modes_keep_the_input_order():
     n = 12
     circ = W.random_circuit(n, 100, seed=4) + [("I", (3,), ())]
-    for enc, kw in [("c128", {"fusion": 1}), ("c64", {"fusion": 1}), ("compact", {}),
+    for enc, kw in [("c128", {"fusion": 1}), ("c64", {"fusion": 1}), ("compact", {"fusion": 1}),
                     ("compact", {"compact_mode": PER_BLOCK, "fusion": 1})]:
         order, blen, fused = schedule(n, enc, circ, **kw)
         assert order == non_identity(circ)
@@ -124,3 +126,60 @@ def test_schedule_errors():
     with pytest.raises(jq.JqError) as e:
         jq.plan_schedule(2, "c128", [("H", (0,), ()), ("H", (2,), ())])
     assert e.value.code == jq.JQ_EINVAL and "gate 1" in str(e.value)
+
+
+# gates that are exact on the two-byte code (permutations and phase shifts by
+# an integer number of code units: 128 arg / pi is an integer or at least not
+# within 1e-6 of a half-integer)
+CODE_NAMES = {"X", "CNOT", "TOFFOLI", "Z", "S", "T", "S+", "T+", "CZ", "RZ", "U1", "R", "U", "CP"}
+
+
+def is_code_op(g):
+    name, p = g[0], g[2]
+    if name not in CODE_NAMES:
+        return False
+    if name in ("U", "R"):      # phase 2 pi / 2^k: 256 / 2^k code units
+        return int(p[0]) <= 8
+    if name == "CP":            # phase p[0]
+        return not (abs((128 * p[0] / math.pi) % 1 - 0.5) < 1e-6)
+    if name in ("RZ", "U1"):
+        d = 128 * p[0] / 2 / math.pi if name == "RZ" else 128 * p[0] / math.pi
+        return not (abs(d % 1 - 0.5) < 1e-6)
+    return True
+
+
+@pytest.mark.parametrize("n,seed", [(12, 1), (14, 2), (20, 3)])
+def test_compact_per_gate_fuses_only_exact_code_runs(n, seed):
+    # per-gate quantisation: fused blocks hold only ops exact on the codes,
+    # and no gate moves past a gate that decodes (everything before such a
+    # gate in the input stays before it)
+    circ = W.random_circuit(n, 200, seed=seed) + W.rz_cnot_chain(n, 2, seed=seed)
+    order, blen, fused = schedule(n, "compact", circ)
+    assert sorted(order) == non_identity(circ) and any(fused)
+    pos = 0
+    for b, f in zip(blen, fused):
+        if f:
+            assert all(is_code_op(circ[i]) for i in order[pos:pos + b]), [circ[i][0] for i in order[pos:pos + b]]
+        pos += b
+    where = {g: k for k, g in enumerate(order)}
+    for i, g in enumerate(circ):
+        if g[0] == "I" or is_code_op(g):
+            continue
+        before = {j for j in range(i) if circ[j][0] != "I"}
+        assert set(order[:where[i]]) == before, (i, g[0])
+    # tile: lane bits are qubits 0..5, five register qubits
+    pos = 0
+    for b, f in zip(blen, fused):
+        blk = [circ[i] for i in order[pos:pos + b]]
+        pos += b
+        if f:
+            assert len({q for g in blk for q in targets_of(g)} - set(range(6))) <= 5
+
+
+def test_compact_rz_cnot_layer_is_a_few_passes():
+    # the 37-qubit RZ + CNOT-chain layer: 73 gates in a handful of code passes
+    n = 37
+    circ = W.rz_cnot_chain(n, 1, seed=37)
+    order, blen, fused = schedule(n, "compact", circ)
+    # a trailing gate may run alone when that moves fewer bytes than a pass
+    assert len(blen) <= 8 and sum(b for b, f in zip(blen, fused) if f) >= len(circ) - 2, list(blen)
