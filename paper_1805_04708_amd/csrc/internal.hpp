@@ -148,6 +148,9 @@ struct PlanConfig {
     // modulus-preserving phase shifts (exact on the codes) fuse, and no gate
     // moves past one that does not
     bool code_domain = false;
+    // R register slots fixed to qubits 0..R-1; the F fixed lane bits are
+    // then qubits R..R+F-1 (R = 0: lane bit b is qubit b)
+    int fixed_reg_bits = 0;
 };
 
 struct Plan {
@@ -218,8 +221,10 @@ void cp_shorbox(const CompactBufs& b, int n, int n_x, uint64_t G, uint64_t y, hi
 // code plane is read in runs of 2^F bytes)
 constexpr int kCpFixedLaneBits = 6;
 // a fused pass of code-domain ops (permutations, integer phase-code shifts)
-// on both code planes, no decoding
-void cp_apply_codes(const CompactBufs& b, int n, const FPass& pass, int k_reg, hipStream_t st);
+// on both code planes, no decoding; qubits 0 and 1 in register slots 0 and
+// 1 (fixed_reg_bits = kCpCodeRegBits), lane bits qubits 2..7
+constexpr int kCpCodeRegBits = 2;
+void cp_apply_codes(const CompactBufs& b, int n, const FPass& pass, int k_reg, int fixed_reg_bits, hipStream_t st);
 // one fused pass quantised once: decode, the pass's ops in FP64, range
 // (unless every gate of the block keeps all moduli), encode
 void cp_apply_block(const CompactBufs& b, int n, const FPass& pass, int k_reg, int fixed_lane_bits,

@@ -703,6 +703,8 @@ __device__ __forceinline__ void code_perm_lane(uint32_t (&c)[1 << K], int b, uin
         const uint32_t partner = (uint32_t)__shfl_xor((int)c[s], mask, 64);
         const bool ok = thr_ok && ((uint32_t)s & rc) == rc;
         c[s] = ok ? partner : c[s];
+        // a few exchanges in flight at a time, not one result register per slot
+        if ((s & 7) == 7) JQ_SLOT_FENCE();
     }
 }
 
@@ -790,28 +792,53 @@ __device__ __forceinline__ void code_perm_reg_dispatch(uint32_t (&c)[1 << K], in
     }
 }
 
-// Waves loop over the tiles (a launch holds at most 2^32 threads).
-template <int K>
+// Waves loop over the tiles (a launch holds at most 2^32 threads).  With
+// R = 2 register slots 0 and 1 are qubits 0 and 1 and the lane bits qubits
+// 2..7: a lane then moves its four consecutive codes of a plane with one
+// 4-byte access (256-byte runs per wave instruction) and unpacks them into
+// slots.
+template <int K, int R>
 __global__ __launch_bounds__(kBlock) void k_cp_codes(int8_t* __restrict__ b0, int8_t* __restrict__ b1, FPass P,
                                                       const FOp* __restrict__ ops, uint64_t ntiles) {
     constexpr int S = 1 << K;
-    const int lane = threadIdx.x & 63;
+    constexpr int W = 1 << R;  // codes per access
+    const uint32_t lane = threadIdx.x & 63;
     const uint64_t wpb = blockDim.x >> 6;
     const uint64_t wave0 = (uint64_t)blockIdx.x * wpb + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * wpb;
+    // lane bits are qubits R..R+5: a lane's codes start at byte lane * W of
+    // the tile's (wave-uniform) base, and the register slots' offsets are
+    // uniform too, so every access is a scalar pointer plus the lane's
+    // 32-bit byte offset
+    const uint64_t lane_off = (uint64_t)lane << R;
+    const uint32_t lane_b = lane << R;
     uint64_t stride[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) stride[j] = 1ull << P.reg_q[j];
     for (uint64_t w = wave0; w < ntiles; w += nwaves) {
-    const uint64_t base = tile_base(P, w, (uint64_t)lane);
+    const uint64_t t0 = tile_base(P, w, 0);
+    // readfirstlane returns int: each half goes through uint32_t so the low
+    // half is not sign-extended into the high one
+    const uint64_t ubase = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t0 >> 32)) << 32) |
+                           (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t0);
+    const uint64_t base = ubase | lane_off;
     uint32_t c[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        uint64_t off = 0;
+    for (int sh = 0; sh < S; sh += W) {
+        uint64_t off = ubase;
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (s & (1 << j)) off += stride[j];
-        c[s] = (uint32_t)(uint8_t)b0[base + off] | ((uint32_t)(uint8_t)b1[base + off] << 8);
+        for (int j = R; j < K; ++j)
+            if (sh & (1 << j)) off += stride[j];
+        const int8_t* p0 = b0 + off;
+        const int8_t* p1 = b1 + off;
+        if constexpr (W == 4) {
+            const uint32_t x0 = *reinterpret_cast<const uint32_t*>(p0 + lane_b);
+            const uint32_t x1 = *reinterpret_cast<const uint32_t*>(p1 + lane_b);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) c[sh + k] = ((x0 >> (8 * k)) & 0xffu) | (((x1 >> (8 * k)) & 0xffu) << 8);
+        } else {
+            c[sh] = (uint32_t)(uint8_t)p0[lane_b] | ((uint32_t)(uint8_t)p1[lane_b] << 8);
+        }
     }
     for (int k = 0; k < P.n_ops; ++k) {
         const FOp* op = ops + k;
@@ -823,17 +850,32 @@ __global__ __launch_bounds__(kBlock) void k_cp_codes(int8_t* __restrict__ b0, in
             default: break;
         }
     }
-    uint64_t sbase = base;
-    asm volatile("" : "+v"(sbase));
+    // the store addresses are recomputed from a fresh copy of the base,
+    // not kept live in registers across the ops
+    uint64_t sbase = ubase;
+    asm volatile("" : "+s"(sbase));
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        uint64_t off = 0;
+    for (int sh = 0; sh < S; sh += W) {
+        uint64_t off = sbase;
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-            if (s & (1 << j)) off += stride[j];
-        const uint32_t lo = c[s] & 0xffu;
-        b0[sbase + off] = (int8_t)lo;
-        b1[sbase + off] = (int8_t)(lo == 0x80u ? 0u : (c[s] >> 8) & 0xffu);
+        for (int j = R; j < K; ++j)
+            if (sh & (1 << j)) off += stride[j];
+        int8_t* p0 = b0 + off;
+        int8_t* p1 = b1 + off;
+        uint32_t y0 = 0, y1 = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const uint32_t lo = c[sh + k] & 0xffu;
+            y0 |= lo << (8 * k);
+            y1 |= (lo == 0x80u ? 0u : (c[sh + k] >> 8) & 0xffu) << (8 * k);
+        }
+        if constexpr (W == 4) {
+            *reinterpret_cast<uint32_t*>(p0 + lane_b) = y0;
+            *reinterpret_cast<uint32_t*>(p1 + lane_b) = y1;
+        } else {
+            p0[lane_b] = (int8_t)y0;
+            p1[lane_b] = (int8_t)y1;
+        }
     }
     }
 }
@@ -1058,7 +1100,7 @@ void launch_cp_fused(const CompactBufs& b, int n, const FPass& pass, bool keeps,
 
 namespace {
 
-template <int K>
+template <int K, int R>
 void launch_cp_codes(const CompactBufs& b, int n, const FPass& pass, hipStream_t st) {
     const uint64_t dim = 1ull << n;
     const uint64_t ntiles = 1ull << (n - 6 - K);
@@ -1066,24 +1108,33 @@ void launch_cp_codes(const CompactBufs& b, int n, const FPass& pass, hipStream_t
     const uint64_t need = ntiles / wpb;
     // up to 2^20 blocks of 4 waves; larger states loop over their tiles
     const unsigned blocks = (unsigned)(need < (1ull << 20) ? need : (1ull << 20));
-    hipLaunchKernelGGL((k_cp_codes<K>), dim3(blocks), dim3(64 * wpb), 0, st, b.codes, b.codes + dim, pass, pass.ops,
-                       ntiles);
+    hipLaunchKernelGGL((k_cp_codes<K, R>), dim3(blocks), dim3(64 * wpb), 0, st, b.codes, b.codes + dim, pass,
+                       pass.ops, ntiles);
     JQ_HIP(hipGetLastError());
 }
 
 }  // namespace
 
-void cp_apply_codes(const CompactBufs& b, int n, const FPass& pass, int k_reg, hipStream_t st) {
+void cp_apply_codes(const CompactBufs& b, int n, const FPass& pass, int k_reg, int fixed_reg_bits, hipStream_t st) {
     if (n < 6 + k_reg) fail(JQ_EINVAL, "compact code pass: state smaller than a tile");
-    switch (k_reg) {
-        case 2: launch_cp_codes<2>(b, n, pass, st); break;
-        case 3: launch_cp_codes<3>(b, n, pass, st); break;
-        case 4: launch_cp_codes<4>(b, n, pass, st); break;
-        case 5: launch_cp_codes<5>(b, n, pass, st); break;
-        case 6: launch_cp_codes<6>(b, n, pass, st); break;
-        case 7: launch_cp_codes<7>(b, n, pass, st); break;
-        default: fail(JQ_EINVAL, "compact code pass: register bits must be 2..7");
+    if (fixed_reg_bits == kCpCodeRegBits) {
+        // the kernel addresses slots 0, 1 as qubits 0, 1 and lane bit b as
+        // qubit 2 + b
+        bool ok = pass.reg_q[0] == 0 && pass.reg_q[1] == 1;
+        for (int q = 0; q < 6; ++q) ok = ok && pass.lane_q[q] == 2 + q;
+        if (!ok) fail(JQ_EDEVICE, "compact code pass: tile layout does not match");
+        switch (k_reg) {
+            case 2: launch_cp_codes<2, 2>(b, n, pass, st); break;
+            case 3: launch_cp_codes<3, 2>(b, n, pass, st); break;
+            case 4: launch_cp_codes<4, 2>(b, n, pass, st); break;
+            case 5: launch_cp_codes<5, 2>(b, n, pass, st); break;
+            case 6: launch_cp_codes<6, 2>(b, n, pass, st); break;
+            case 7: launch_cp_codes<7, 2>(b, n, pass, st); break;
+            default: fail(JQ_EINVAL, "compact code pass: register bits must be 2..7");
+        }
+        return;
     }
+    fail(JQ_EINVAL, "compact code pass: unsupported layout");
 }
 
 void cp_apply_block(const CompactBufs& b, int n, const FPass& pass, int k_reg, int fixed_lane_bits, bool keeps,

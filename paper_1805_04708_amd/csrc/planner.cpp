@@ -22,23 +22,25 @@ namespace jq {
 
 namespace {
 
+// Qubits 0..R+F-1 are always in the tile (R fixed register slots, then F
+// fixed lane bits); the builder places the other targets.
 struct PassBuilder {
-    int n, F, K, max_ops;
-    std::vector<int> reg_q;   // qubits in register slots
+    int n, F, K, max_ops, R;
+    std::vector<int> reg_q;   // qubits in the free register slots R..K-1
     std::vector<int> lane_q;  // qubits in lane bits F..5
     std::vector<int> taken;   // op indices
     uint64_t tile() const {
-        uint64_t t = (1ull << F) - 1;
+        uint64_t t = (1ull << (R + F)) - 1;
         for (int q : reg_q) t |= 1ull << q;
         for (int q : lane_q) t |= 1ull << q;
         return t;
     }
     // can target q be placed (or is it already)?  Places it if so.
     bool place(int q) {
-        if (q < F) return true;
+        if (q < R + F) return true;
         if (std::find(reg_q.begin(), reg_q.end(), q) != reg_q.end()) return true;
         if (std::find(lane_q.begin(), lane_q.end(), q) != lane_q.end()) return true;
-        if ((int)reg_q.size() < K) { reg_q.push_back(q); return true; }
+        if ((int)reg_q.size() < K - R) { reg_q.push_back(q); return true; }
         if ((int)lane_q.size() < 6 - F) { lane_q.push_back(q); return true; }
         return false;
     }
@@ -77,8 +79,7 @@ FOp lower_fop(const GateOp& op, const FPass& p, int F, int K, int nmux = 0, cons
         return -1;
     };
     auto lane_of = [&](int q) {
-        if (q < F) return q;
-        for (int b = F; b < 6; b++) if (p.lane_q[b] == q) return b;
+        for (int b = 0; b < 6; b++) if (p.lane_q[b] == q) return b;
         return -1;
     };
     uint64_t reg_bits = 0;
@@ -319,7 +320,7 @@ void merge_same_target(std::vector<PassOp>& ops) {
 Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
     Plan plan;
     const int n = cfg.n, F = cfg.fixed_lane_bits, K = cfg.k_reg;
-    const bool can_fuse = cfg.fuse && K >= 1 && n >= 6 + K && 6 + K <= kMaxTileBits;
+    const bool can_fuse = cfg.fuse && K >= 1 && K >= cfg.fixed_reg_bits && n >= 6 + K && 6 + K <= kMaxTileBits;
     if (!can_fuse) {
         for (const auto& op : ops) {
             Step s;
@@ -334,7 +335,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
     for (size_t i = 0; i < ops.size(); i++) remaining[i] = (int)i;
     const size_t window = 4096;
     while (!remaining.empty()) {
-        PassBuilder pb{n, F, K, cfg.max_ops, {}, {}, {}};
+        PassBuilder pb{n, F, K, cfg.max_ops, cfg.fixed_reg_bits, {}, {}, {}};
         uint64_t blk_any = 0, blk_diag = 0;
         size_t scanned = 0;
         for (size_t r = 0; r < remaining.size() && scanned < window; r++, scanned++) {
@@ -399,15 +400,16 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
                 if (!(t & (1ull << q))) { t |= 1ull << q; return q; }
             fail(JQ_EDEVICE, "planner: no free qubit");
         };
+        const int R = cfg.fixed_reg_bits;
         while ((int)pb.lane_q.size() < 6 - F) pb.lane_q.push_back(next_free());
-        while ((int)pb.reg_q.size() < K) pb.reg_q.push_back(next_free());
+        while ((int)pb.reg_q.size() < K - R) pb.reg_q.push_back(next_free());
         Step s;
         s.fused = true;
         s.k_reg = K;
         FPass& p = s.pass;
         std::memset(&p, 0, sizeof(p));
-        for (int j = 0; j < 8; j++) p.reg_q[j] = j < K ? pb.reg_q[j] : -1;
-        for (int b = 0; b < 6; b++) p.lane_q[b] = b < F ? b : pb.lane_q[b - F];
+        for (int j = 0; j < 8; j++) p.reg_q[j] = j < R ? j : j < K ? pb.reg_q[j - R] : -1;
+        for (int b = 0; b < 6; b++) p.lane_q[b] = b < F ? R + b : pb.lane_q[b - F];
         std::vector<int> tb;
         for (int b = 0; b < 6; b++) tb.push_back(p.lane_q[b]);
         for (int j = 0; j < K; j++) tb.push_back(p.reg_q[j]);

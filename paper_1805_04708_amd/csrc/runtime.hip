@@ -195,6 +195,7 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
     }
     if (c.code_domain) {
         c.absorb = false;
+        c.fixed_reg_bits = kCpCodeRegBits;
         if (!(opts && opts->fusion >= 2)) c.k_reg = 5;
     }
     while (c.fuse && c.k_reg > 2 && c.n < 6 + c.k_reg) c.k_reg--;
@@ -250,7 +251,7 @@ void apply_ops(jq_state* s, const std::vector<GateOp>& ops, const PlanConfig& cf
         p.ops = dev + step.first_fop;
         if (s->enc == JQ_COMPACT && cfg.code_domain) {
             Timed t(s, K_CP_CODES, 2.0 * sweep);
-            cp_apply_codes(compact_bufs(s), s->n, p, step.k_reg, s->stream);
+            cp_apply_codes(compact_bufs(s), s->n, p, step.k_reg, cfg.fixed_reg_bits, s->stream);
             continue;
         }
         if (s->enc == JQ_COMPACT) {

@@ -119,10 +119,26 @@ def test_n37_two_byte_code_ghz_and_phases():
         assert abs(s.norm() - 1.0) < 1e-14
         # uniform state, one layer of RZ and the CNOT chain: moduli never change
         s.init(jq.JQ_INIT_UNIFORM)
-        s.apply_circuit(W.rz_cnot_chain(n, 1, seed=5))
+        circ = W.rz_cnot_chain(n, 1, seed=5)
+        s.apply_circuit(circ)
         b0, b1, rng = s.codes(0, 1 << 12)
         assert np.all(b0 == -127) and abs(rng[0] - 2.0 ** (-n / 2)) < 1e-30
         assert abs(s.norm() - 1.0) < 1e-13
+        # phase codes one by one, all over the index range (tiles whose base
+        # has bit 31 and above set): follow a source index through the
+        # circuit; each RZ adds its entry's phase in code units, 128 arg / pi
+        # rounded, mod 256 (a phase of 0 to start), each CNOT moves the index
+        src = np.random.default_rng(371).integers(0, 1 << n, 48)
+        for j in [int(x) for x in src] + [(1 << n) - 1, 1 << 31, (1 << 36) | 12345]:
+            i, code = j, 0
+            for name, q, p in circ:
+                if name == "RZ":
+                    e = OG.matrix("RZ", p)[(i >> q[0]) & 1, (i >> q[0]) & 1]
+                    code = ((code + int(np.rint(128 * np.angle(e) / math.pi)) + 128) & 255) - 128
+                elif (i >> q[0]) & 1:
+                    i ^= 1 << q[1]
+            c0, c1, _ = s.codes(i, 1)
+            assert int(c0[0]) == -127 and int(c1[0]) == code, (j, i)
         # sampling at 2^37 amplitudes (the block sums loop over their blocks):
         # every probability is the same rounded value of 2^-37, so the event
         # is floor(u 2^37) up to the rounding of the cumulative sums

@@ -167,13 +167,14 @@ def test_compact_per_gate_fuses_only_exact_code_runs(n, seed):
             continue
         before = {j for j in range(i) if circ[j][0] != "I"}
         assert set(order[:where[i]]) == before, (i, g[0])
-    # tile: lane bits are qubits 0..5, five register qubits
+    # tile: qubits 0, 1 in register slots, lane bits qubits 2..7, five more
+    # register qubits
     pos = 0
     for b, f in zip(blen, fused):
         blk = [circ[i] for i in order[pos:pos + b]]
         pos += b
         if f:
-            assert len({q for g in blk for q in targets_of(g)} - set(range(6))) <= 5
+            assert len({q for g in blk for q in targets_of(g)} - set(range(8))) <= 5
 
 
 def test_compact_rz_cnot_layer_is_a_few_passes():
