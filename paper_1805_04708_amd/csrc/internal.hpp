@@ -112,6 +112,13 @@ struct FOp {
     // dense: matrix v (v = multiplexer value, first selector the MSB) at
     // m[8v .. 8v+7] as m00 m01 m10 m11; diag: d0..d3
     double m[32];
+    // code-domain phase shift as cs_n masked adds: slot s of a thread gets
+    // cs_add[t] (phase-code units in bits 8..15) where (s & cs_reg[t]) ==
+    // cs_reg[t] and the thread's index has every bit of cs_thr[t] set
+    int32_t cs_n;
+    uint32_t cs_reg[4];
+    uint32_t cs_add[4];
+    uint64_t cs_thr[4];
 };
 
 constexpr int kMaxTileBits = 16;

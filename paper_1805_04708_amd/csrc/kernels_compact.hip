@@ -713,66 +713,76 @@ __device__ __forceinline__ void code_perm_lane(uint32_t (&c)[1 << K], int b, uin
 // so the sum is taken mod 256 as one shift after another would be, and a
 // pending sum travels with its amplitude through later permutations.  The
 // rule that zero amplitudes (b0 = -128) keep phase code 0 is applied at the
-// store (every stored state has phase code 0 on its zero amplitudes).
-// R0: register slot of the selector, or -1 when the shift is the same for
-// all slots of the thread (no selector, or one held by the thread).
-template <int K, int R0>
-__device__ __forceinline__ void code_shift_t(uint32_t (&c)[1 << K], uint32_t d0, uint32_t d1, uint32_t rc,
-                                             bool thr_ok) {
-    const uint32_t e0 = thr_ok ? d0 : 0u, e1 = thr_ok ? d1 : 0u;
-    if (rc == 0) {
+// store (every stored state has phase code 0 on its zero amplitudes).  A
+// shift arrives as up to four masked adds of one value per thread (its
+// selector and control bits outside the slots decide the value, those in
+// the slots the mask).
+template <int K>
+__device__ __forceinline__ void code_masked_add(uint32_t (&c)[1 << K], uint32_t m, uint32_t e) {
 #pragma unroll
-        for (int s = 0; s < (1 << K); ++s) c[s] += (R0 >= 0 && ((s >> R0) & 1)) ? e1 : e0;
-    } else {
+    for (int s = 0; s < (1 << K); ++s) {
+        c[s] += ((uint32_t)s & m) == m ? e : 0u;
+        if ((s & 7) == 7) JQ_SLOT_FENCE();
+    }
+}
+
+// slots with bit J set (a selector in register slot J, no register control)
+template <int K, int J>
+__device__ __forceinline__ void code_add_bit(uint32_t (&c)[1 << K], uint32_t e) {
+    if constexpr (J < K) {
 #pragma unroll
-        for (int s = 0; s < (1 << K); ++s) {
-            const uint32_t e = (R0 >= 0 && ((s >> R0) & 1)) ? e1 : e0;
-            c[s] += ((uint32_t)s & rc) == rc ? e : 0u;
-        }
+        for (int s = 0; s < (1 << K); ++s)
+            if (s & (1 << J)) c[s] += e;
     }
 }
 
 template <int K>
-__device__ __forceinline__ void code_shift(uint32_t (&c)[1 << K], const FOp* op, uint64_t base, bool thr_ok) {
-    const uint32_t rc = op->reg_ctrl;
-    const int nsel = op->nsel;
-    uint32_t sh[4];
+__device__ __forceinline__ void code_add_mask(uint32_t (&c)[1 << K], uint32_t m, uint32_t e) {
+    if (m == 0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) sh[i] = (uint32_t)(int)op->m[i] << 8;
-    const int g0 = op->sel_glob[0] >= 0 ? (int)((base >> op->sel_glob[0]) & 1) : 0;
-    if (nsel == 0) {
-        code_shift_t<K, -1>(c, sh[0], sh[0], rc, thr_ok);
-    } else if (nsel == 1 && op->sel_reg[0] < 0) {
-        const uint32_t d = g0 ? sh[1] : sh[0];
-        code_shift_t<K, -1>(c, d, d, rc, thr_ok);
-    } else if (nsel == 1) {
-        // one case per selector slot, each closed by its own empty asm
-        // statement (see code_perm_reg_dispatch)
-        switch (op->sel_reg[0]) {
-            case 0: code_shift_t<K, 0>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 0"); break;
-            case 1: code_shift_t<K, 1>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 1"); break;
-            case 2: code_shift_t<K, 2>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 2"); break;
-            case 3: code_shift_t<K, 3>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 3"); break;
-            case 4: code_shift_t<K, 4>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 4"); break;
-            case 5: code_shift_t<K, 5>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 5"); break;
-            case 6: code_shift_t<K, 6>(c, sh[0], sh[1], rc, thr_ok); asm volatile("; shift slot 6"); break;
-            default: break;
-        }
-    } else {
-        // two selectors (a general two-qubit diagonal): per slot
-        const int g1 = op->sel_glob[1] >= 0 ? (int)((base >> op->sel_glob[1]) & 1) : 0;
-        const int r0 = op->sel_reg[0], r1 = op->sel_reg[1];
-#pragma unroll
-        for (int s = 0; s < (1 << K); ++s) {
-            const int v = 2 * (r0 >= 0 ? (s >> r0) & 1 : g0) + (r1 >= 0 ? (s >> r1) & 1 : g1);
-            uint32_t d = sh[0];
-            d = v == 1 ? sh[1] : d;
-            d = v == 2 ? sh[2] : d;
-            d = v == 3 ? sh[3] : d;
-            const bool ok = thr_ok && ((uint32_t)s & rc) == rc;
-            c[s] += ok ? d : 0u;
-        }
+        for (int s = 0; s < (1 << K); ++s) c[s] += e;
+        return;
     }
+    // one case per slot, each closed by its own empty asm statement (see
+    // code_perm_reg_dispatch)
+    switch (m) {
+        case 1u: code_add_bit<K, 0>(c, e); asm volatile("; add slot 0"); return;
+        case 2u: code_add_bit<K, 1>(c, e); asm volatile("; add slot 1"); return;
+        case 4u: code_add_bit<K, 2>(c, e); asm volatile("; add slot 2"); return;
+        case 8u: code_add_bit<K, 3>(c, e); asm volatile("; add slot 3"); return;
+        case 16u: code_add_bit<K, 4>(c, e); asm volatile("; add slot 4"); return;
+        case 32u: code_add_bit<K, 5>(c, e); asm volatile("; add slot 5"); return;
+        case 64u: code_add_bit<K, 6>(c, e); asm volatile("; add slot 6"); return;
+        default: code_masked_add<K>(c, m, e); return;
+    }
+}
+
+// A term that reaches every slot of a thread goes into the thread's pending
+// sum acc instead (added to all its slots before the next cross-lane
+// exchange and at the store): register permutations leave a value common
+// to all slots of the thread where it is, and adds commute.
+template <int K>
+__device__ __forceinline__ void code_shift(uint32_t (&c)[1 << K], uint32_t& acc, const FOp* op, uint64_t base) {
+    // the op's fields are wave-uniform: read them into scalar registers
+    // before any per-thread choice
+    const int nt = __builtin_amdgcn_readfirstlane(op->cs_n);
+    for (int t = 0; t < nt; ++t) {
+        const uint64_t tm = op->cs_thr[t];
+        const uint32_t m = (uint32_t)__builtin_amdgcn_readfirstlane((int)op->cs_reg[t]);
+        const uint32_t add = (uint32_t)__builtin_amdgcn_readfirstlane((int)op->cs_add[t]);
+        const uint32_t e = (base & tm) == tm ? add : 0u;
+        if (m == 0)
+            acc += e;
+        else
+            code_add_mask<K>(c, m, e);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void code_flush(uint32_t (&c)[1 << K], uint32_t& acc) {
+#pragma unroll
+    for (int s = 0; s < (1 << K); ++s) c[s] += acc;
+    acc = 0;
 }
 
 // Each case ends in its own empty asm statement so that the compiler cannot
@@ -840,13 +850,22 @@ __global__ __launch_bounds__(kBlock) void k_cp_codes(int8_t* __restrict__ b0, in
             c[sh] = (uint32_t)(uint8_t)p0[lane_b] | ((uint32_t)(uint8_t)p1[lane_b] << 8);
         }
     }
+    uint32_t acc = 0;
+    bool pending = false;  // wave-uniform: some term went into acc
     for (int k = 0; k < P.n_ops; ++k) {
         const FOp* op = ops + k;
         const bool thr_ok = (base & op->thr_ctrl) == op->thr_ctrl;
         switch (op->kind) {
             case F_PERM_REG: code_perm_reg_dispatch<K>(c, op->slot, op->reg_ctrl, thr_ok); break;
-            case F_PERM_LANE: code_perm_lane<K>(c, op->slot, op->reg_ctrl, thr_ok); break;
-            case F_CSHIFT: code_shift<K>(c, op, base, thr_ok); break;
+            case F_PERM_LANE:
+                if (pending) code_flush<K>(c, acc);
+                pending = false;
+                code_perm_lane<K>(c, op->slot, op->reg_ctrl, thr_ok);
+                break;
+            case F_CSHIFT:
+                code_shift<K>(c, acc, op, base);
+                pending = true;
+                break;
             default: break;
         }
     }
@@ -867,7 +886,7 @@ __global__ __launch_bounds__(kBlock) void k_cp_codes(int8_t* __restrict__ b0, in
         for (int k = 0; k < W; ++k) {
             const uint32_t lo = c[sh + k] & 0xffu;
             y0 |= lo << (8 * k);
-            y1 |= (lo == 0x80u ? 0u : (c[sh + k] >> 8) & 0xffu) << (8 * k);
+            y1 |= (lo == 0x80u ? 0u : ((c[sh + k] + acc) >> 8) & 0xffu) << (8 * k);
         }
         if constexpr (W == 4) {
             *reinterpret_cast<uint32_t*>(p0 + lane_b) = y0;

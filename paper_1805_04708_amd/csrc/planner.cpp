@@ -134,7 +134,39 @@ FOp lower_fop(const GateOp& op, const FPass& p, int F, int K, int nmux = 0, cons
         }
         double d[4];
         phase_code_shifts(op, d);
-        for (int i = 0; i < 4; i++) f.m[i] = std::rint(d[i]);
+        int64_t m[4];
+        for (int i = 0; i < 4; i++) {
+            f.m[i] = std::rint(d[i]);
+            m[i] = (int64_t)f.m[i];
+        }
+        // the shift for selector values (v0, v1) (first selector the MSB) is
+        // m[2 v0 + v1] = A + B v0 + C v1 + D v0 v1 (one selector: m[v0] =
+        // A + B v0), each term added where its selector bits are 1; the sums
+        // are exact integers and only their value mod 256 is kept
+        int64_t coef[4] = {m[0], 0, 0, 0};
+        if (op.nsel == 1) coef[1] = m[1] - m[0];
+        if (op.nsel == 2) {
+            coef[1] = m[2] - m[0];
+            coef[2] = m[1] - m[0];
+            coef[3] = m[3] - m[2] - m[1] + m[0];
+        }
+        // term t holds the selectors of its bits (bit 0: first, bit 1: second)
+        f.cs_n = 0;
+        for (int t = 0; t < 4; t++) {
+            const uint32_t add = (uint32_t)(coef[t] & 255) << 8;
+            if (add == 0) continue;
+            uint32_t rm = f.reg_ctrl;
+            uint64_t tm = f.thr_ctrl;
+            for (int i = 0; i < 2; i++) {
+                if (!(t >> i & 1)) continue;
+                if (f.sel_reg[i] >= 0) rm |= 1u << f.sel_reg[i];
+                else tm |= 1ull << f.sel_glob[i];
+            }
+            f.cs_reg[f.cs_n] = rm;
+            f.cs_thr[f.cs_n] = tm;
+            f.cs_add[f.cs_n] = add;
+            f.cs_n++;
+        }
         return f;
     }
     if (op.kind == OP_DIAG) {
