@@ -61,6 +61,9 @@ def parse():
     p.add_argument("--seed", type=int, default=2018)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true")
+    p.add_argument("--extras", default="all", metavar="LIST",
+                   help="comma-separated extras to run (per_target, c64, batch, serve, compact, compact_dense, "
+                        "shor, aux, large), or all")
     p.add_argument("--cpu-gates", type=int, default=3, help="gates of the circuit the CPU oracle times")
     p.add_argument("--copy-calibration", type=int, default=4096, metavar="MIB",
                    help="size of the plain torch device copy reported as the copy ceiling (and used to "
@@ -203,21 +206,22 @@ def main():
                                           (PEAK_FP64_TFLOPS if args.enc == "c128" else PEAK_FP32_TFLOPS),
                                   "alg_flops_per_launch": flops}
 
-    if not args.no_extras:
+    wanted = set() if args.no_extras else (
+        {"per_target", "c64", "batch", "serve", "compact", "compact_dense", "shor", "aux", "large"}
+        if args.extras == "all" else set(args.extras.split(",")))
+    if "per_target" in wanted:
         out["per_target"] = per_target(state, n, bpa)
 
     state.close()
     torch.cuda.synchronize()
 
-    if not args.no_extras:
-        out["c64_same_circuit"] = c64_same_circuit(n, circuit, args.fusion)
-        out["batch"] = batch_extra()
-        out["serve"] = serve_extra()
-        out["compact"] = compact_extra()
-        out["compact_dense"] = compact_dense_extra()
-        out["shor"] = shor_extra()
-        out["aux"] = aux_extra()
-        out["large_states"] = large_extra()
+    extras = [("c64", "c64_same_circuit", lambda: c64_same_circuit(n, circuit, args.fusion)),
+              ("batch", "batch", batch_extra), ("serve", "serve", serve_extra),
+              ("compact", "compact", compact_extra), ("compact_dense", "compact_dense", compact_dense_extra),
+              ("shor", "shor", shor_extra), ("aux", "aux", aux_extra), ("large", "large_states", large_extra)]
+    for name, key, fn in extras:
+        if name in wanted:
+            out[key] = fn()
 
     if args.copy_calibration:
         # a plain device copy: the practical streaming ceiling of this GPU,

@@ -675,94 +675,155 @@ __global__ __launch_bounds__(kBlock) void k_cp_shorbox(int8_t* __restrict__ b0, 
 // modulus-preserving phase shift adds an integer to the phase code of each
 // touched non-zero amplitude (the per-gate kernels above); both are exact
 // on the codes, so a run of them executes as one tile pass over both planes
-// without decoding, with the codes they would produce one by one.  A lane
-// holds 2^K (b0, b1) pairs packed in 32-bit registers (b0 in bits 0-7, b1 in
-// bits 8 and up, reduced mod 256 at the store); lane bits are index bits
-// 0..5, so each plane is read and written in runs of 64 bytes.
+// without decoding, with the codes they would produce one by one.
+//
+// Tile: register slot bits 0 and 1 are qubits 0 and 1, lane bits qubits
+// 2..7, slot bits 2..K-1 qubits the planner picks.  A lane moves four
+// consecutive codes of a plane with one 4-byte access (256-byte runs per
+// wave instruction).  Two codes share a 32-bit register: register r holds
+// slot 2r in bits 0-15 and slot 2r+1 in bits 16-31, each as b0 in the low
+// byte and b1 in the high byte of its half.  A phase shift adds to the high
+// byte of a half with a 16-bit add, so the sum is taken mod 256 and never
+// reaches b0 or the other half; a pending sum travels with its amplitude
+// through later permutations.  Zero amplitudes (b0 = -128) get phase code 0
+// at the store, as every stored state has on its zero amplitudes.
 
-template <int K, int J>
-__device__ __forceinline__ void code_perm_reg(uint32_t (&c)[1 << K], uint32_t rc, bool thr_ok) {
-    if constexpr (J < K) {
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// 16-bit add in each half (no carry between the halves)
+__device__ __forceinline__ uint32_t add16x2(uint32_t x, uint32_t y) {
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, x) + __builtin_bit_cast(u16x2, y));
+}
+
+// the two halves of x exchanged
+__device__ __forceinline__ uint32_t swap_halves(uint32_t x) { return (x << 16) | (x >> 16); }
+
+// permutation of slot bit J >= 1: registers r and r | 2^(J-1) exchange
+// (whole registers, or only their high halves when slot bit 0 is a control)
+template <int P, int J>
+__device__ __forceinline__ void hc_perm_reg(uint32_t (&c)[P], uint32_t rc, bool thr_ok) {
+    constexpr int B = 1 << (J - 1);
+    if constexpr (B < P) {
+        const uint32_t rr = rc >> 1;
+        if (!(rc & 1u)) {
 #pragma unroll
-        for (int s = 0; s < (1 << K); ++s) {
-            if (s & (1 << J)) continue;
-            const int t = s | (1 << J);
-            const bool ok = thr_ok && ((uint32_t)s & rc) == rc;
-            const uint32_t x = c[s], y = c[t];
-            c[s] = ok ? y : x;
-            c[t] = ok ? x : y;
+            for (int r = 0; r < P; ++r) {
+                if (r & B) continue;
+                const bool ok = thr_ok && ((uint32_t)r & rr) == rr;
+                const uint32_t x = c[r], y = c[r | B];
+                c[r] = ok ? y : x;
+                c[r | B] = ok ? x : y;
+            }
+        } else {
+            const uint32_t hi = thr_ok ? 0xffff0000u : 0u;
+#pragma unroll
+            for (int r = 0; r < P; ++r) {
+                if (r & B) continue;
+                const uint32_t msk = ((uint32_t)r & rr) == rr ? hi : 0u;
+                const uint32_t x = c[r], y = c[r | B];
+                c[r] = (y & msk) | (x & ~msk);
+                c[r | B] = (x & msk) | (y & ~msk);
+            }
         }
     }
 }
 
-template <int K>
-__device__ __forceinline__ void code_perm_lane(uint32_t (&c)[1 << K], int b, uint32_t rc, bool thr_ok) {
+// permutation of slot bit 0: the halves of each register exchange
+template <int P>
+__device__ __forceinline__ void hc_perm_half(uint32_t (&c)[P], uint32_t rc, bool thr_ok) {
+    const uint32_t rr = rc >> 1;
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const bool ok = thr_ok && ((uint32_t)r & rr) == rr;
+        c[r] = ok ? swap_halves(c[r]) : c[r];
+    }
+}
+
+// Each case ends in its own empty asm statement so that the compiler cannot
+// merge the cases into one body with a run-time register index (which would
+// move the register tile to scratch memory).
+template <int P>
+__device__ __forceinline__ void hc_perm_reg_dispatch(uint32_t (&c)[P], int j, uint32_t rc, bool thr_ok) {
+    switch (j) {
+        case 0: hc_perm_half<P>(c, rc, thr_ok); asm volatile("; code slot 0"); break;
+        case 1: hc_perm_reg<P, 1>(c, rc, thr_ok); asm volatile("; code slot 1"); break;
+        case 2: hc_perm_reg<P, 2>(c, rc, thr_ok); asm volatile("; code slot 2"); break;
+        case 3: hc_perm_reg<P, 3>(c, rc, thr_ok); asm volatile("; code slot 3"); break;
+        case 4: hc_perm_reg<P, 4>(c, rc, thr_ok); asm volatile("; code slot 4"); break;
+        case 5: hc_perm_reg<P, 5>(c, rc, thr_ok); asm volatile("; code slot 5"); break;
+        case 6: hc_perm_reg<P, 6>(c, rc, thr_ok); asm volatile("; code slot 6"); break;
+        case 7: hc_perm_reg<P, 7>(c, rc, thr_ok); asm volatile("; code slot 7"); break;
+        default: break;
+    }
+}
+
+// permutation of lane bit b: codes move between lanes 2^b apart (whole
+// registers, or only the high halves when slot bit 0 is a control)
+template <int P>
+__device__ __forceinline__ void hc_perm_lane(uint32_t (&c)[P], int b, uint32_t rc, bool thr_ok) {
     const int mask = 1 << b;
+    const uint32_t rr = rc >> 1;
+    const uint32_t keep = (rc & 1u) ? 0x0000ffffu : 0u;
 #pragma unroll
-    for (int s = 0; s < (1 << K); ++s) {
-        const uint32_t partner = (uint32_t)__shfl_xor((int)c[s], mask, 64);
-        const bool ok = thr_ok && ((uint32_t)s & rc) == rc;
-        c[s] = ok ? partner : c[s];
+    for (int r = 0; r < P; ++r) {
+        const uint32_t partner = (uint32_t)__shfl_xor((int)c[r], mask, 64);
+        const bool ok = thr_ok && ((uint32_t)r & rr) == rr;
+        c[r] = ok ? (partner & ~keep) | (c[r] & keep) : c[r];
         // a few exchanges in flight at a time, not one result register per slot
-        if ((s & 7) == 7) JQ_SLOT_FENCE();
+        if ((r & 7) == 7) JQ_SLOT_FENCE();
     }
 }
 
-// Phase shifts add into bits 8.. of the packed register: the carry out of
-// the phase byte lands in bits 16.. and is dropped when the codes are stored,
-// so the sum is taken mod 256 as one shift after another would be, and a
-// pending sum travels with its amplitude through later permutations.  The
-// rule that zero amplitudes (b0 = -128) keep phase code 0 is applied at the
-// store (every stored state has phase code 0 on its zero amplitudes).  A
-// shift arrives as up to four masked adds of one value per thread (its
-// selector and control bits outside the slots decide the value, those in
-// the slots the mask).
-template <int K>
-__device__ __forceinline__ void code_masked_add(uint32_t (&c)[1 << K], uint32_t m, uint32_t e) {
+// registers whose bit J-1 is set get y added (a selector in slot J >= 1)
+template <int P, int J>
+__device__ __forceinline__ void hc_add_bit(uint32_t (&c)[P], uint32_t y) {
+    constexpr int B = 1 << (J - 1);
+    if constexpr (B < P) {
 #pragma unroll
-    for (int s = 0; s < (1 << K); ++s) {
-        c[s] += ((uint32_t)s & m) == m ? e : 0u;
-        if ((s & 7) == 7) JQ_SLOT_FENCE();
+        for (int r = 0; r < P; ++r)
+            if (r & B) c[r] = add16x2(c[r], y);
     }
 }
 
-// slots with bit J set (a selector in register slot J, no register control)
-template <int K, int J>
-__device__ __forceinline__ void code_add_bit(uint32_t (&c)[1 << K], uint32_t e) {
-    if constexpr (J < K) {
+// Slot s gets e (phase-code units in bits 8..15) where (s & m) == m.
+template <int P>
+__device__ __forceinline__ void hc_add_mask(uint32_t (&c)[P], uint32_t m, uint32_t e) {
+    const uint32_t both = e | (e << 16), hi = e << 16;
+    // the halves to add to: both, or only the high one when slot bit 0 is
+    // in the mask; the registers by the mask's other bits
+    const uint32_t y = (m & 1u) ? hi : both;
+    const uint32_t rm = m >> 1;
+    if (rm == 0) {
 #pragma unroll
-        for (int s = 0; s < (1 << K); ++s)
-            if (s & (1 << J)) c[s] += e;
-    }
-}
-
-template <int K>
-__device__ __forceinline__ void code_add_mask(uint32_t (&c)[1 << K], uint32_t m, uint32_t e) {
-    if (m == 0) {
-#pragma unroll
-        for (int s = 0; s < (1 << K); ++s) c[s] += e;
+        for (int r = 0; r < P; ++r) c[r] = add16x2(c[r], y);
         return;
     }
-    // one case per slot, each closed by its own empty asm statement (see
-    // code_perm_reg_dispatch)
-    switch (m) {
-        case 1u: code_add_bit<K, 0>(c, e); asm volatile("; add slot 0"); return;
-        case 2u: code_add_bit<K, 1>(c, e); asm volatile("; add slot 1"); return;
-        case 4u: code_add_bit<K, 2>(c, e); asm volatile("; add slot 2"); return;
-        case 8u: code_add_bit<K, 3>(c, e); asm volatile("; add slot 3"); return;
-        case 16u: code_add_bit<K, 4>(c, e); asm volatile("; add slot 4"); return;
-        case 32u: code_add_bit<K, 5>(c, e); asm volatile("; add slot 5"); return;
-        case 64u: code_add_bit<K, 6>(c, e); asm volatile("; add slot 6"); return;
-        default: code_masked_add<K>(c, m, e); return;
+    switch (rm) {
+        case 1u: hc_add_bit<P, 1>(c, y); asm volatile("; add slot 1"); return;
+        case 2u: hc_add_bit<P, 2>(c, y); asm volatile("; add slot 2"); return;
+        case 4u: hc_add_bit<P, 3>(c, y); asm volatile("; add slot 3"); return;
+        case 8u: hc_add_bit<P, 4>(c, y); asm volatile("; add slot 4"); return;
+        case 16u: hc_add_bit<P, 5>(c, y); asm volatile("; add slot 5"); return;
+        case 32u: hc_add_bit<P, 6>(c, y); asm volatile("; add slot 6"); return;
+        case 64u: hc_add_bit<P, 7>(c, y); asm volatile("; add slot 7"); return;
+        default: break;
+    }
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        c[r] = add16x2(c[r], ((uint32_t)r & rm) == rm ? y : 0u);
+        if ((r & 7) == 7) JQ_SLOT_FENCE();
     }
 }
 
-// A term that reaches every slot of a thread goes into the thread's pending
-// sum acc instead (added to all its slots before the next cross-lane
-// exchange and at the store): register permutations leave a value common
-// to all slots of the thread where it is, and adds commute.
-template <int K>
-__device__ __forceinline__ void code_shift(uint32_t (&c)[1 << K], uint32_t& acc, const FOp* op, uint64_t base) {
+// A shift arrives as up to four masked adds of one value per thread (its
+// selector and control bits outside the slots decide the value, those in
+// the slots the mask).  A term that reaches every slot of a thread goes
+// into the thread's pending sum acc instead (added to all its slots before
+// the next cross-lane exchange and at the store): register permutations
+// leave a value common to all slots of the thread where it is, and adds
+// commute.
+template <int P>
+__device__ __forceinline__ void hc_shift(uint32_t (&c)[P], uint32_t& acc, const FOp* op, uint64_t base) {
     // the op's fields are wave-uniform: read them into scalar registers
     // before any per-thread choice
     const int nt = __builtin_amdgcn_readfirstlane(op->cs_n);
@@ -774,54 +835,31 @@ __device__ __forceinline__ void code_shift(uint32_t (&c)[1 << K], uint32_t& acc,
         if (m == 0)
             acc += e;
         else
-            code_add_mask<K>(c, m, e);
+            hc_add_mask<P>(c, m, e);
     }
 }
 
-template <int K>
-__device__ __forceinline__ void code_flush(uint32_t (&c)[1 << K], uint32_t& acc) {
+template <int P>
+__device__ __forceinline__ void hc_flush(uint32_t (&c)[P], uint32_t& acc) {
+    const uint32_t y = (acc & 0xff00u) * 0x10001u;
 #pragma unroll
-    for (int s = 0; s < (1 << K); ++s) c[s] += acc;
+    for (int r = 0; r < P; ++r) c[r] = add16x2(c[r], y);
     acc = 0;
 }
 
-// Each case ends in its own empty asm statement so that the compiler cannot
-// merge the cases into one body with a run-time register index (which would
-// move the register tile to scratch memory).
+// Waves loop over the tiles (a launch holds at most 2^32 threads).
 template <int K>
-__device__ __forceinline__ void code_perm_reg_dispatch(uint32_t (&c)[1 << K], int j, uint32_t rc, bool thr_ok) {
-    switch (j) {
-        case 0: code_perm_reg<K, 0>(c, rc, thr_ok); asm volatile("; code slot 0"); break;
-        case 1: code_perm_reg<K, 1>(c, rc, thr_ok); asm volatile("; code slot 1"); break;
-        case 2: code_perm_reg<K, 2>(c, rc, thr_ok); asm volatile("; code slot 2"); break;
-        case 3: code_perm_reg<K, 3>(c, rc, thr_ok); asm volatile("; code slot 3"); break;
-        case 4: code_perm_reg<K, 4>(c, rc, thr_ok); asm volatile("; code slot 4"); break;
-        case 5: code_perm_reg<K, 5>(c, rc, thr_ok); asm volatile("; code slot 5"); break;
-        case 6: code_perm_reg<K, 6>(c, rc, thr_ok); asm volatile("; code slot 6"); break;
-        default: break;
-    }
-}
-
-// Waves loop over the tiles (a launch holds at most 2^32 threads).  With
-// R = 2 register slots 0 and 1 are qubits 0 and 1 and the lane bits qubits
-// 2..7: a lane then moves its four consecutive codes of a plane with one
-// 4-byte access (256-byte runs per wave instruction) and unpacks them into
-// slots.
-template <int K, int R>
 __global__ __launch_bounds__(kBlock) void k_cp_codes(int8_t* __restrict__ b0, int8_t* __restrict__ b1, FPass P,
                                                       const FOp* __restrict__ ops, uint64_t ntiles) {
-    constexpr int S = 1 << K;
-    constexpr int W = 1 << R;  // codes per access
+    constexpr int NP = 1 << (K - 1);  // registers, two codes each
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t wpb = blockDim.x >> 6;
     const uint64_t wave0 = (uint64_t)blockIdx.x * wpb + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * wpb;
-    // lane bits are qubits R..R+5: a lane's codes start at byte lane * W of
-    // the tile's (wave-uniform) base, and the register slots' offsets are
-    // uniform too, so every access is a scalar pointer plus the lane's
-    // 32-bit byte offset
-    const uint64_t lane_off = (uint64_t)lane << R;
-    const uint32_t lane_b = lane << R;
+    // a lane's codes start at byte 4 lane of the tile's (wave-uniform) base,
+    // and the slots' offsets are uniform too, so every access is a scalar
+    // pointer plus the lane's 32-bit byte offset
+    const uint32_t lane_b = lane << 2;
     uint64_t stride[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) stride[j] = 1ull << P.reg_q[j];
@@ -831,24 +869,19 @@ __global__ __launch_bounds__(kBlock) void k_cp_codes(int8_t* __restrict__ b0, in
     // half is not sign-extended into the high one
     const uint64_t ubase = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t0 >> 32)) << 32) |
                            (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t0);
-    const uint64_t base = ubase | lane_off;
-    uint32_t c[S];
+    const uint64_t base = ubase | (uint64_t)lane_b;
+    uint32_t c[NP];
 #pragma unroll
-    for (int sh = 0; sh < S; sh += W) {
+    for (int sh = 0; sh < (1 << K); sh += 4) {
         uint64_t off = ubase;
 #pragma unroll
-        for (int j = R; j < K; ++j)
+        for (int j = 2; j < K; ++j)
             if (sh & (1 << j)) off += stride[j];
-        const int8_t* p0 = b0 + off;
-        const int8_t* p1 = b1 + off;
-        if constexpr (W == 4) {
-            const uint32_t x0 = *reinterpret_cast<const uint32_t*>(p0 + lane_b);
-            const uint32_t x1 = *reinterpret_cast<const uint32_t*>(p1 + lane_b);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) c[sh + k] = ((x0 >> (8 * k)) & 0xffu) | (((x1 >> (8 * k)) & 0xffu) << 8);
-        } else {
-            c[sh] = (uint32_t)(uint8_t)p0[lane_b] | ((uint32_t)(uint8_t)p1[lane_b] << 8);
-        }
+        const uint32_t x0 = *reinterpret_cast<const uint32_t*>(b0 + off + lane_b);
+        const uint32_t x1 = *reinterpret_cast<const uint32_t*>(b1 + off + lane_b);
+        // bytes (b0, b1) of slots sh, sh+1 and of sh+2, sh+3
+        c[sh / 2] = __builtin_amdgcn_perm(x1, x0, 0x05010400u);
+        c[sh / 2 + 1] = __builtin_amdgcn_perm(x1, x0, 0x07030602u);
     }
     uint32_t acc = 0;
     bool pending = false;  // wave-uniform: some term went into acc
@@ -856,45 +889,39 @@ __global__ __launch_bounds__(kBlock) void k_cp_codes(int8_t* __restrict__ b0, in
         const FOp* op = ops + k;
         const bool thr_ok = (base & op->thr_ctrl) == op->thr_ctrl;
         switch (op->kind) {
-            case F_PERM_REG: code_perm_reg_dispatch<K>(c, op->slot, op->reg_ctrl, thr_ok); break;
+            case F_PERM_REG: hc_perm_reg_dispatch<NP>(c, op->slot, op->reg_ctrl, thr_ok); break;
             case F_PERM_LANE:
-                if (pending) code_flush<K>(c, acc);
+                if (pending) hc_flush<NP>(c, acc);
                 pending = false;
-                code_perm_lane<K>(c, op->slot, op->reg_ctrl, thr_ok);
+                hc_perm_lane<NP>(c, op->slot, op->reg_ctrl, thr_ok);
                 break;
             case F_CSHIFT:
-                code_shift<K>(c, acc, op, base);
+                hc_shift<NP>(c, acc, op, base);
                 pending = true;
                 break;
             default: break;
         }
     }
+    if (pending) hc_flush<NP>(c, acc);
     // the store addresses are recomputed from a fresh copy of the base,
     // not kept live in registers across the ops
     uint64_t sbase = ubase;
     asm volatile("" : "+s"(sbase));
 #pragma unroll
-    for (int sh = 0; sh < S; sh += W) {
+    for (int sh = 0; sh < (1 << K); sh += 4) {
         uint64_t off = sbase;
 #pragma unroll
-        for (int j = R; j < K; ++j)
+        for (int j = 2; j < K; ++j)
             if (sh & (1 << j)) off += stride[j];
-        int8_t* p0 = b0 + off;
-        int8_t* p1 = b1 + off;
-        uint32_t y0 = 0, y1 = 0;
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            const uint32_t lo = c[sh + k] & 0xffu;
-            y0 |= lo << (8 * k);
-            y1 |= (lo == 0x80u ? 0u : ((c[sh + k] + acc) >> 8) & 0xffu) << (8 * k);
-        }
-        if constexpr (W == 4) {
-            *reinterpret_cast<uint32_t*>(p0 + lane_b) = y0;
-            *reinterpret_cast<uint32_t*>(p1 + lane_b) = y1;
-        } else {
-            p0[lane_b] = (int8_t)y0;
-            p1[lane_b] = (int8_t)y1;
-        }
+        const uint32_t lo = c[sh / 2], hi = c[sh / 2 + 1];
+        const uint32_t y0 = __builtin_amdgcn_perm(hi, lo, 0x06040200u);
+        uint32_t y1 = __builtin_amdgcn_perm(hi, lo, 0x07050301u);
+        // bytes of y0 equal to 0x80 (zero amplitudes): exact per-byte test
+        const uint32_t t = y0 ^ 0x80808080u;
+        const uint32_t z = ~(((t & 0x7f7f7f7fu) + 0x7f7f7f7fu) | t) & 0x80808080u;
+        y1 &= ~(z | (z - (z >> 7)));
+        *reinterpret_cast<uint32_t*>(b0 + off + lane_b) = y0;
+        *reinterpret_cast<uint32_t*>(b1 + off + lane_b) = y1;
     }
     }
 }
@@ -1119,7 +1146,7 @@ void launch_cp_fused(const CompactBufs& b, int n, const FPass& pass, bool keeps,
 
 namespace {
 
-template <int K, int R>
+template <int K>
 void launch_cp_codes(const CompactBufs& b, int n, const FPass& pass, hipStream_t st) {
     const uint64_t dim = 1ull << n;
     const uint64_t ntiles = 1ull << (n - 6 - K);
@@ -1127,7 +1154,7 @@ void launch_cp_codes(const CompactBufs& b, int n, const FPass& pass, hipStream_t
     const uint64_t need = ntiles / wpb;
     // up to 2^20 blocks of 4 waves; larger states loop over their tiles
     const unsigned blocks = (unsigned)(need < (1ull << 20) ? need : (1ull << 20));
-    hipLaunchKernelGGL((k_cp_codes<K, R>), dim3(blocks), dim3(64 * wpb), 0, st, b.codes, b.codes + dim, pass,
+    hipLaunchKernelGGL((k_cp_codes<K>), dim3(blocks), dim3(64 * wpb), 0, st, b.codes, b.codes + dim, pass,
                        pass.ops, ntiles);
     JQ_HIP(hipGetLastError());
 }
@@ -1143,12 +1170,12 @@ void cp_apply_codes(const CompactBufs& b, int n, const FPass& pass, int k_reg, i
         for (int q = 0; q < 6; ++q) ok = ok && pass.lane_q[q] == 2 + q;
         if (!ok) fail(JQ_EDEVICE, "compact code pass: tile layout does not match");
         switch (k_reg) {
-            case 2: launch_cp_codes<2, 2>(b, n, pass, st); break;
-            case 3: launch_cp_codes<3, 2>(b, n, pass, st); break;
-            case 4: launch_cp_codes<4, 2>(b, n, pass, st); break;
-            case 5: launch_cp_codes<5, 2>(b, n, pass, st); break;
-            case 6: launch_cp_codes<6, 2>(b, n, pass, st); break;
-            case 7: launch_cp_codes<7, 2>(b, n, pass, st); break;
+            case 2: launch_cp_codes<2>(b, n, pass, st); break;
+            case 3: launch_cp_codes<3>(b, n, pass, st); break;
+            case 4: launch_cp_codes<4>(b, n, pass, st); break;
+            case 5: launch_cp_codes<5>(b, n, pass, st); break;
+            case 6: launch_cp_codes<6>(b, n, pass, st); break;
+            case 7: launch_cp_codes<7>(b, n, pass, st); break;
             default: fail(JQ_EINVAL, "compact code pass: register bits must be 2..7");
         }
         return;

@@ -196,7 +196,7 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
     if (c.code_domain) {
         c.absorb = false;
         c.fixed_reg_bits = kCpCodeRegBits;
-        if (!(opts && opts->fusion >= 2)) c.k_reg = 6;
+        if (!(opts && opts->fusion >= 2)) c.k_reg = 7;
     }
     while (c.fuse && c.k_reg > 2 && c.n < 6 + c.k_reg) c.k_reg--;
     return c;

@@ -77,3 +77,34 @@ def test_full_size_layer_bit_identical():
     n = 28
     fused, single = run_both(n, W.rz_cnot_chain(n, 2, seed=28), init=jq.JQ_INIT_UNIFORM)
     assert_same(fused, single)
+
+
+@pytest.mark.parametrize("fusion", [0, 3, 4, 5, 6, 7])
+def test_qubit0_controls_selectors_and_targets(fusion):
+    # two codes share a register in the code pass (qubit 0 picks the half):
+    # controls and selectors on qubit 0 act on one half of every register,
+    # a target on qubit 0 swaps the halves; every tile depth K
+    n = 16
+    rng = np.random.default_rng(70 + fusion)
+    circ = [("H", (q,), ()) for q in range(n)]
+    for _ in range(150):
+        t = int(rng.integers(1, n))
+        u = int(rng.choice([q for q in range(1, n) if q != t]))
+        circ.append([("CNOT", (0, t), ()), ("TOFFOLI", (0, u, t), ()), ("CNOT", (t, 0), ()),
+                     ("X", (0,), (), (t,)), ("CZ", (0, t), ()), ("CP", (0, t), (float(rng.uniform(-3, 3)),)),
+                     ("RZ", (0,), (float(rng.uniform(0, 6.2)),)), ("U1", (t,), (float(rng.uniform(-3, 3)),), (0,)),
+                     ("CP", (t, u), (float(rng.uniform(-3, 3)),)), ("X", (t,), (), (0, u))][int(rng.integers(10))])
+    b0 = rng.integers(-127, 127, 1 << n).astype(np.int8)
+    b1 = rng.integers(-128, 128, 1 << n).astype(np.int8)
+    b0[rng.random(1 << n) < 0.2] = -128
+    b1[b0 == -128] = 0
+    out = []
+    for fu in (fusion, 1):
+        with jq.State(n, "compact") as s:
+            s.write_codes(b0, b1, (0.01, 0.3))
+            s.apply_circuit(circ, fusion=fu)
+            out.append(s.codes())
+    assert_same(out[0], out[1])
+    if fusion != 1:
+        _, blen, fused = jq.plan_schedule(n, "compact", circ, fusion=fusion)
+        assert fused.any()
