@@ -493,8 +493,8 @@ def aux_extra(n=48, pairs=20, m=64, seed=48):
             "seconds": dt, "max_abs_amplitude": float(np.max(np.abs(amp)))}
 
 
-def large_extra():
-    """One layer of the RZ + CNOT-chain circuit on 256 GiB states: N=34
+def large_extra(layers=20):
+    """The RZ + CNOT-chain circuit (20 layers) on 256 GiB states: N=34
     complex128 and N=37 two-byte code, from the uniform state."""
     from paper_1805_04708_amd import jq
     from paper_1805_04708_amd import workloads as W
@@ -506,7 +506,7 @@ def large_extra():
         except Exception as e:  # not enough HBM on this device
             out[f"{enc}_n{n}"] = {"error": str(e)}
             continue
-        circ = W.rz_cnot_chain(n, 1, seed=n)
+        circ = W.rz_cnot_chain(n, layers, seed=n)
         arr = jq.gates(circ)
         s.synchronize()
         s.profile(True)

@@ -105,6 +105,31 @@ def test_n34_c128_uniform_and_ghz():
         assert np.allclose(s.probabilities([0, 17, n - 1]), [0.5, 0, 0, 0, 0, 0, 0, 0.5], atol=1e-12)
 
 
+def test_n34_c128_twenty_rz_cnot_layers():
+    # the 34-qubit complex128 workload: 20 layers of RZ and the CNOT chain
+    # from the uniform state; every amplitude is 2^(-17) times the product
+    # of the RZ entries met along its source index's path through the
+    # circuit (each CNOT moves the index)
+    n = 34
+    if free_gib() < 257:
+        pytest.skip("needs 256 GiB of free HBM")
+    circ = W.rz_cnot_chain(n, 20, seed=34)
+    with jq.State(n, "c128") as s:
+        s.init(jq.JQ_INIT_UNIFORM)
+        s.apply_circuit(circ)
+        assert abs(s.norm() - 1.0) < 1e-12
+        src = np.random.default_rng(341).integers(0, 1 << n, 32)
+        for j in [int(x) for x in src] + [0, (1 << n) - 1, (1 << 33) | 777]:
+            i, amp = j, complex(2.0 ** (-n / 2))
+            for name, q, p in circ:
+                if name == "RZ":
+                    amp *= OG.matrix("RZ", p)[(i >> q[0]) & 1, (i >> q[0]) & 1]
+                elif (i >> q[0]) & 1:
+                    i ^= 1 << q[1]
+            got = s.amplitudes(i, 1)[0]
+            assert abs(got - amp) < 1e-12 * abs(amp), (j, i, got, amp)
+
+
 def test_n37_two_byte_code_ghz_and_phases():
     n = 37
     if free_gib() < 257:
@@ -117,9 +142,10 @@ def test_n37_two_byte_code_ghz_and_phases():
         b0, b1, rng = s.codes((1 << n) - 4, 4)
         assert list(b0) == [-128, -128, -128, -127] and rng[0] == rng[1]
         assert abs(s.norm() - 1.0) < 1e-14
-        # uniform state, one layer of RZ and the CNOT chain: moduli never change
+        # uniform state, 20 layers of RZ and the CNOT chain (the 37-qubit
+        # two-byte workload): moduli never change
         s.init(jq.JQ_INIT_UNIFORM)
-        circ = W.rz_cnot_chain(n, 1, seed=5)
+        circ = W.rz_cnot_chain(n, 20, seed=5)
         s.apply_circuit(circ)
         b0, b1, rng = s.codes(0, 1 << 12)
         assert np.all(b0 == -127) and abs(rng[0] - 2.0 ** (-n / 2)) < 1e-30
