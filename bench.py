@@ -107,9 +107,16 @@ def cpu_baseline(n, circuit, gates):
     O.run(psi, n, sample)
     dt = time.perf_counter() - t0
     del psi
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((line.split(":", 1)[1].strip() for line in f if line.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": len(sample) / dt, "unit": "gates/s", "cores": 1, "kind": "oracle",
             "sample": f"first {len(sample)} gates of the same circuit at N={n}, single-threaded FP64 C oracle, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "host": {"nproc": os.cpu_count(), "model": model}}
 
 
 def main():
@@ -207,10 +214,14 @@ def main():
                                   "alg_flops_per_launch": flops}
 
     wanted = set() if args.no_extras else (
-        {"per_target", "c64", "batch", "serve", "compact", "compact_dense", "shor", "aux", "large"}
+        {"per_target", "unfused", "c64", "batch", "serve", "compact", "compact_dense", "shor", "aux", "large",
+         "paper_circuits"}
         if args.extras == "all" else set(args.extras.split(",")))
     if "per_target" in wanted:
         out["per_target"] = per_target(state, n, bpa)
+        out["cz_by_min_qubit"] = cz_by_min_qubit(state, n)
+    if "unfused" in wanted:
+        out["unfused"] = unfused_extra(state, circuit, args.layers)
 
     state.close()
     torch.cuda.synchronize()
@@ -218,7 +229,8 @@ def main():
     extras = [("c64", "c64_same_circuit", lambda: c64_same_circuit(n, circuit, args.fusion)),
               ("batch", "batch", batch_extra), ("serve", "serve", serve_extra),
               ("compact", "compact", compact_extra), ("compact_dense", "compact_dense", compact_dense_extra),
-              ("shor", "shor", shor_extra), ("aux", "aux", aux_extra), ("large", "large_states", large_extra)]
+              ("shor", "shor", shor_extra), ("aux", "aux", aux_extra), ("large", "large_states", large_extra),
+              ("paper_circuits", "paper_circuits", paper_circuits_extra)]
     for name, key, fn in extras:
         if name in wanted:
             out[key] = fn()
@@ -292,27 +304,31 @@ def batch_extra(count=4096, seed=4096):
     return res
 
 
-def serve_extra(count=2000, seed=77, enc="c64"):
-    """Poisson arrivals of layered circuits, N in 10..28 with weight 2^(-N/2),
-    depth 20..200: the request loop vs the plain one-at-a-time path."""
-    import numpy as np
-    import torch
+def _mean_service(enc, seed, count=200):
+    """Mean time per request of the plain path (unfused per-gate kernels,
+    one stream, one circuit at a time) over a probe trace."""
     from paper_1805_04708_amd import jq
     from paper_1805_04708_amd import workloads as W
 
-    probe = W.serving_trace(200, 1.0, seed + 1)
-    lowered = [(n, jq.gates(c)) for _, n, c in probe]
-    # service rate of the plain path: unfused per-gate kernels, one stream
+    lowered = [(n, jq.gates(c)) for _, n, c in W.serving_trace(count, 1.0, seed)]
     t0 = time.perf_counter()
     for n, arr in lowered:
         with jq.State(n, enc) as s:
             s.apply_circuit(arr, fusion=1)
             s.norm()
-    mean_service = (time.perf_counter() - t0) / len(lowered)
-    rate = 0.9 / mean_service
-    trace = W.serving_trace(count, rate, seed)
-    reqs = [(t, n, jq.gates(c)) for t, n, c in trace]
+    return (time.perf_counter() - t0) / len(lowered)
 
+
+def _serve_run(enc, rate, count, seed):
+    """One Poisson trace at the given rate through the plain path and through
+    the request loop: latency = arrival to device completion."""
+    import threading
+
+    import numpy as np
+    from paper_1805_04708_amd import jq
+    from paper_1805_04708_amd import workloads as W
+
+    reqs = [(t, n, jq.gates(c)) for t, n, c in W.serving_trace(count, rate, seed)]
     # plain path: each request waits for the previous one
     lat_seq = []
     start = time.perf_counter()
@@ -327,7 +343,6 @@ def serve_extra(count=2000, seed=77, enc="c64"):
     seq_span = time.perf_counter() - start
 
     sv = jq.Server(hbm_budget=280 << 30, n_streams=4, queue_cap=count, encoding=enc)
-    import threading
     lat, lags = [], []
 
     def drain():
@@ -352,13 +367,35 @@ def serve_extra(count=2000, seed=77, enc="c64"):
     st = sv.stats()
     sv.close()
     lat_all = np.array(lat) + np.array(lags[:len(lat)])
-    return {"requests": count, "encoding": enc, "arrival_rate_per_s": rate,
-            "served": {"p50_ms": float(np.percentile(lat_all, 50)), "p99_ms": float(np.percentile(lat_all, 99)),
+    return {"served": {"p50_ms": float(np.percentile(lat_all, 50)), "p99_ms": float(np.percentile(lat_all, 99)),
                        "throughput_per_s": count / span, "peak_resident_bytes": st["peak_resident_bytes"]},
             "sequential_plain": {"p50_ms": float(np.percentile(lat_seq, 50)),
-                                 "p99_ms": float(np.percentile(lat_seq, 99)), "throughput_per_s": count / seq_span},
-            "note": "latency = arrival to device completion; the plain path runs one circuit at a time "
-                    "with one kernel per gate"}
+                                 "p99_ms": float(np.percentile(lat_seq, 99)), "throughput_per_s": count / seq_span}}
+
+
+def serve_extra(count=2000, seed=77):
+    """Poisson arrivals of layered circuits, N in 10..28 with weight 2^(-N/2),
+    depth 20..200: the request loop vs the plain one-at-a-time path.  The
+    arrival rate is a fraction (load) of the plain path's measured service
+    rate: complex64 at load 0.9 (the headline), a sweep of the load, and the
+    two-byte code at load 0.9 on a shorter trace."""
+    out = {"requests": count, "encoding": "c64"}
+    mean_c64 = _mean_service("c64", seed + 1)
+    rate = 0.9 / mean_c64
+    out["arrival_rate_per_s"] = rate
+    out["plain_mean_service_ms"] = 1000 * mean_c64
+    out.update(_serve_run("c64", rate, count, seed))
+    out["load_sweep"] = {}
+    for load in (0.5, 1.2):
+        r = _serve_run("c64", load / mean_c64, count // 2, seed + 10)
+        out["load_sweep"][str(load)] = {"arrival_rate_per_s": load / mean_c64, "requests": count // 2, **r}
+    mean_cp = _mean_service("compact", seed + 2, count=50)
+    n_cp = 200
+    out["compact"] = {"requests": n_cp, "arrival_rate_per_s": 0.9 / mean_cp, "plain_mean_service_ms": 1000 * mean_cp,
+                      **_serve_run("compact", 0.9 / mean_cp, n_cp, seed + 20)}
+    out["note"] = ("latency = arrival to device completion; the plain path runs one circuit at a time with one "
+                   "kernel per gate")
+    return out
 
 
 def compact_extra(n=30, layers=20):
@@ -520,6 +557,87 @@ def large_extra(layers=20):
                               "norm_minus_1": nrm - 1.0, "state_gib": (16 if enc == "c128" else 2) * 2 ** n / 2 ** 30,
                               "kernels": {k: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"],
                                               "gbps": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in st.items()}}
+    return out
+
+
+def unfused_extra(state, circuit, total_layers, layers=10):
+    """The first layers of the same circuit with one kernel per gate
+    (fusion off): gates/s and the per-kernel split, beside the fused figure."""
+    from paper_1805_04708_amd import jq
+
+    layers = min(layers, total_layers)
+    sub = circuit[:layers * (len(circuit) // total_layers)]
+    arr = jq.gates(sub)
+    state.init(jq.JQ_INIT_ZERO)
+    state.apply_circuit(jq.gates(sub[:8]), fusion=1)  # warm-up
+    state.synchronize()
+    state.init(jq.JQ_INIT_ZERO)
+    state.synchronize()
+    state.profile(True)
+    t0 = time.perf_counter()
+    state.apply_circuit(arr, fusion=1)
+    state.synchronize()
+    dt = time.perf_counter() - t0
+    st = state.profile_read()
+    state.profile(False)
+    return {"gates": len(sub), "layers": layers, "seconds": dt, "gates_per_s": len(sub) / dt,
+            "kernels": {k: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"],
+                            "gbps": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in st.items()}}
+
+
+def cz_by_min_qubit(state, n):
+    """Unfused CZ(t, t+1) by its lower qubit t: GB/s of the diagonal kernel
+    (a quarter of the state is read and written)."""
+    res = {}
+    for t in range(n - 1):
+        state.profile(True)
+        state.apply_circuit([("CZ", (t, t + 1), ())] * 3, fusion=1)
+        s = state.profile_read()["diag"]
+        state.profile(False)
+        res[t] = round(s["bytes"] / (s["ms"] * 1e-3) / 1e9, 1)
+    return res
+
+
+# The paper's elapsed times per gate used to normalise its weak-scaling
+# figures (Sec. 5.1: Figs. scaling1a/1b for H on every qubit, scaling2/3
+# for the GHZ circuit), in seconds, on whole CPU supercomputer partitions;
+# context only.
+PAPER_NORMALISATION_S = {
+    "hadamard_c128_n32": {"JUQUEEN": 1.2, "K": 1.0, "Sunway": 7.7, "JURECA": 1.9, "JUWELS": 1.3},
+    "hadamard_compact_n35": {"JUQUEEN": 10.7, "K": 30.8, "Sunway": 101.2, "JURECA": 9.7, "JUWELS": 4.7},
+    "ghz_c128_n32": {"JUQUEEN": 0.98, "Sunway": 5.1, "JURECA": 1.4, "JUWELS": 0.9},
+    "ghz_compact_n35": {"JUQUEEN": 2.7, "K": 3.8, "Sunway": 19.9, "JURECA": 2.4, "JUWELS": 2.2},
+}
+
+
+def paper_circuits_extra():
+    """The paper's scaling circuits at its normalisation sizes: H on every
+    qubit and the GHZ circuit (H on qubit 0, then the CNOT chain) from
+    |0...0>, N=32 complex128 and N=35 two-byte code (64 GiB each); seconds
+    per gate with the default plan and with one kernel per gate."""
+    from paper_1805_04708_amd import jq
+    from paper_1805_04708_amd import workloads as W
+
+    out = {}
+    for n, enc in ((32, "c128"), (35, "compact")):
+        try:
+            s = jq.State(n, enc)
+        except Exception as e:  # not enough HBM on this device
+            out[f"{enc}_n{n}"] = {"error": str(e)}
+            continue
+        for name, circ in (("hadamard", W.hadamard_all(n)), ("ghz", W.ghz(n))):
+            arr = jq.gates(circ)
+            row = {"gates": len(circ), "paper_s_per_gate": PAPER_NORMALISATION_S[f"{name}_{enc}_n{n}"]}
+            for label, fusion in (("default", 0), ("one_kernel_per_gate", 1)):
+                s.init(jq.JQ_INIT_ZERO)
+                s.synchronize()
+                t0 = time.perf_counter()
+                s.apply_circuit(arr, fusion=fusion)
+                s.synchronize()
+                dt = time.perf_counter() - t0
+                row[label] = {"seconds": dt, "s_per_gate": dt / len(circ)}
+            out[f"{name}_{enc}_n{n}"] = row
+        s.close()
     return out
 
 
