@@ -327,7 +327,12 @@ typedef struct jq_batch jq_batch;
 /* Prepare count independent circuits (each 1 <= N <= 20) for one
  * persistent launch: gates are lowered and packed into device memory and a
  * packed state arena is allocated.  enc is JQ_C128 or JQ_C64.  Work runs on
- * hip_stream (NULL = the library's stream). */
+ * hip_stream (NULL = the library's stream).  opts->fusion sets the fusion
+ * depth of every circuit: 1..3 = blocks of consecutive gates on at most that
+ * many target qubits; 4 = register/lane tile passes (as for a single large
+ * state) for states too large for LDS, blocks of 3 for the others; 0 or
+ * opts NULL = chosen per (encoding, N) by timing on first use in the
+ * process. */
 int jq_batch_create(const jq_circuit *circuits, size_t count, jq_encoding enc, const jq_exec_opts *opts,
                     void *hip_stream, jq_batch **out);
 

@@ -13,11 +13,16 @@
 // of the block's qubits for one value of the others), applies all the
 // block's gates in registers, and writes them back; one barrier per block.
 // Diagonal gates and controls are tested on each amplitude's full index.
+//
+// Tile mode (depth 4, for states too large for LDS): the circuit runs as the
+// register/lane tile passes of the state-vector planner (many gates per
+// pass, reordered where they commute); the workgroup's waves loop over the
+// state's tiles, one barrier per pass.
 #include <algorithm>
 #include <map>
 #include <mutex>
 
-#include "device_common.hpp"
+#include "fused_ops.hpp"
 
 namespace jq {
 
@@ -45,8 +50,21 @@ struct BCirc {
     int32_t n;
     int32_t first_block;
     int32_t n_blocks;
+    int32_t n_passes;    // tile mode: passes (0: block mode)
+    int32_t first_pass;
     int32_t pad;
     uint64_t state_off;  // amplitude offset in the arena
+};
+
+// fusion depth value that selects tile mode
+constexpr int kTileDepth = 4;
+
+// tile layout per precision, as for single large states: fixed lane bits F
+// (128-byte lines) and register bits K
+template <typename R>
+struct TileShape {
+    static constexpr int K = sizeof(R) == 8 ? 4 : 5;
+    static constexpr int F = sizeof(R) == 8 ? 3 : 4;
 };
 
 constexpr int kBatchThreads = 256;
@@ -243,13 +261,61 @@ __device__ void run_block(typename Vec<R>::T* S, int n, const BBlock& blk, const
     }
 }
 
+// The passes of one circuit over its state psi (2^n amplitudes, in the
+// arena): each wave takes tiles wave, wave + 4, ...; the barrier after each
+// pass makes its stores visible to the next pass's loads (one workgroup, one
+// compute unit).
+template <typename R>
+__device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* passes, int n_passes) {
+    constexpr int K = TileShape<R>::K, F = TileShape<R>::F, S = 1 << K;
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t nw = blockDim.x >> 6;
+    const uint64_t ntiles = 1ull << (n - 6 - K);
+    for (int p = 0; p < n_passes; ++p) {
+        const FPass& P = passes[p];
+        uint64_t lane_off = (uint64_t)(lane & ((1 << F) - 1));
+#pragma unroll
+        for (int b = F; b < 6; ++b) lane_off |= (uint64_t)((lane >> b) & 1) << P.lane_q[b];
+        uint64_t stride[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) stride[j] = 1ull << P.reg_q[j];
+        const FOp* ops = P.ops;
+        const int n_ops = P.n_ops;
+        for (uint64_t t = wave; t < ntiles; t += nw) {
+            uint64_t base = tile_base(P, t, lane_off);
+            Cx<R> a[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                uint64_t off = 0;
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    if (s & (1 << j)) off += stride[j];
+                a[s] = ld<R>(psi, base + off);
+            }
+            run_ops<R, K>(a, ops, n_ops, base, lane);
+            // recompute the store addresses instead of keeping 2^K of them live
+            asm volatile("" : "+v"(base));
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                uint64_t off = 0;
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    if (s & (1 << j)) off += stride[j];
+                st<R>(psi, base + off, a[s]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBatchThreads) void k_batch(typename Vec<R>::T* __restrict__ arena,
                                                           const BCirc* __restrict__ circs,
                                                           const int32_t* __restrict__ order, uint32_t count,
                                                           const BBlock* __restrict__ blocks,
-                                                          const BOp* __restrict__ ops, uint32_t* counter,
-                                                          int lds_max_n) {
+                                                          const BOp* __restrict__ ops, const FPass* __restrict__ passes,
+                                                          uint32_t* counter, int lds_max_n) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     typename Vec<R>::T* lds = reinterpret_cast<typename Vec<R>::T*>(lds_raw);
     __shared__ uint32_t next;
@@ -270,6 +336,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(typename Vec<R>::T* __r
             S[i] = v;
         }
         __syncthreads();
+        if (c.n_passes > 0) {
+            run_tiles<R>(S, n, passes + c.first_pass, c.n_passes);
+            continue;
+        }
         for (int b = 0; b < c.n_blocks; ++b) {
             const BBlock blk = blocks[c.first_block + b];
             switch (blk.k) {
@@ -405,6 +475,8 @@ struct jq_batch {
     void* order = nullptr;
     void* blocks = nullptr;
     void* ops = nullptr;
+    void* passes = nullptr;  // tile mode: FPass per pass, ops pointing into fops
+    void* fops = nullptr;
     uint32_t* counter = nullptr;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -423,7 +495,7 @@ namespace {
 void free_batch(jq_batch* b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
-    for (void* p : {b->arena, b->circs, b->order, b->blocks, b->ops, (void*)b->counter})
+    for (void* p : {b->arena, b->circs, b->order, b->blocks, b->ops, b->passes, b->fops, (void*)b->counter})
         if (p) (void)hipFree(p);
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
@@ -431,29 +503,76 @@ void free_batch(jq_batch* b) {
     delete b;
 }
 
+// Tile mode applies to states in the arena (larger than LDS) that hold a
+// whole tile.
+bool tile_capable(const jq_batch* b, int n) {
+    const int K = b->enc == JQ_C128 ? TileShape<double>::K : TileShape<float>::K;
+    return n > b->lds_max_n && n >= 6 + K;
+}
+
+// The tile passes of one circuit (appended to passes/fops, ops pointers
+// holding fop indices until upload); false if some gate cannot run in a
+// pass (a two-qubit dense gate), in which case the circuit uses blocks.
+bool plan_tiles(const jq_batch* b, size_t i, std::vector<FPass>& passes, std::vector<FOp>& fops) {
+    PlanConfig cfg;
+    cfg.n = b->n[i];
+    cfg.fixed_lane_bits = b->enc == JQ_C128 ? TileShape<double>::F : TileShape<float>::F;
+    cfg.k_reg = b->enc == JQ_C128 ? TileShape<double>::K : TileShape<float>::K;
+    cfg.max_ops = 48;
+    cfg.always_pass = true;
+    Plan plan = make_plan(b->ops_host[i], cfg);
+    for (const Step& st : plan.steps)
+        if (!st.fused) return false;
+    const size_t base = fops.size();
+    for (const Step& st : plan.steps) {
+        FPass p = st.pass;
+        p.ops = reinterpret_cast<const FOp*>((uintptr_t)(base + st.first_fop));  // an index until upload
+        passes.push_back(p);
+    }
+    fops.insert(fops.end(), plan.fops.begin(), plan.fops.end());
+    return true;
+}
+
 // Lay out plans for the given per-circuit depths and upload them.
 void upload_plans(jq_batch* b) {
     std::vector<BCirc> circs(b->count);
     std::vector<BBlock> blocks;
     std::vector<BOp> bops;
+    std::vector<FPass> passes;
+    std::vector<FOp> fops;
     for (size_t i = 0; i < b->count; ++i) {
-        circs[i].n = b->n[i];
-        circs[i].first_block = (int32_t)blocks.size();
-        plan_blocks(b->ops_host[i], b->n[i], b->kb[i], blocks, bops);
-        circs[i].n_blocks = (int32_t)(blocks.size() - circs[i].first_block);
-        circs[i].state_off = b->offs[i];
+        BCirc& c = circs[i];
+        c = BCirc{};
+        c.n = b->n[i];
+        c.state_off = b->offs[i];
+        c.first_block = (int32_t)blocks.size();
+        c.first_pass = (int32_t)passes.size();
+        if (b->kb[i] == kTileDepth && tile_capable(b, b->n[i]) && plan_tiles(b, i, passes, fops)) {
+            c.n_passes = (int32_t)(passes.size() - c.first_pass);
+            c.n_blocks = 0;
+            continue;
+        }
+        plan_blocks(b->ops_host[i], b->n[i], std::min(b->kb[i], 3), blocks, bops);
+        c.n_blocks = (int32_t)(blocks.size() - c.first_block);
     }
     if (bops.empty()) bops.push_back(BOp{});
     if (blocks.empty()) blocks.push_back(BBlock{});
-    for (void* p : {b->circs, b->blocks, b->ops})
+    if (fops.empty()) fops.push_back(FOp{});
+    if (passes.empty()) passes.push_back(FPass{});
+    for (void* p : {b->circs, b->blocks, b->ops, b->passes, b->fops})
         if (p) JQ_HIP(hipFree(p));
-    b->circs = b->blocks = b->ops = nullptr;
+    b->circs = b->blocks = b->ops = b->passes = b->fops = nullptr;
     JQ_HIP(hipMalloc(&b->circs, circs.size() * sizeof(BCirc)));
     JQ_HIP(hipMalloc(&b->blocks, blocks.size() * sizeof(BBlock)));
     JQ_HIP(hipMalloc(&b->ops, bops.size() * sizeof(BOp)));
+    JQ_HIP(hipMalloc(&b->fops, fops.size() * sizeof(FOp)));
+    JQ_HIP(hipMalloc(&b->passes, passes.size() * sizeof(FPass)));
+    for (FPass& p : passes) p.ops = reinterpret_cast<const FOp*>(b->fops) + (uintptr_t)p.ops;
     JQ_HIP(hipMemcpy(b->circs, circs.data(), circs.size() * sizeof(BCirc), hipMemcpyHostToDevice));
     JQ_HIP(hipMemcpy(b->blocks, blocks.data(), blocks.size() * sizeof(BBlock), hipMemcpyHostToDevice));
     JQ_HIP(hipMemcpy(b->ops, bops.data(), bops.size() * sizeof(BOp), hipMemcpyHostToDevice));
+    JQ_HIP(hipMemcpy(b->fops, fops.data(), fops.size() * sizeof(FOp), hipMemcpyHostToDevice));
+    JQ_HIP(hipMemcpy(b->passes, passes.data(), passes.size() * sizeof(FPass), hipMemcpyHostToDevice));
 }
 
 void launch(jq_batch* b) {
@@ -461,13 +580,13 @@ void launch(jq_batch* b) {
     if (b->enc == JQ_C128)
         hipLaunchKernelGGL(k_batch<double>, dim3(b->grid), dim3(kBatchThreads), b->lds_bytes, b->stream,
                            (double2*)b->arena, (const BCirc*)b->circs, (const int32_t*)b->order,
-                           (uint32_t)b->count, (const BBlock*)b->blocks, (const BOp*)b->ops, b->counter,
-                           b->lds_max_n);
+                           (uint32_t)b->count, (const BBlock*)b->blocks, (const BOp*)b->ops,
+                           (const FPass*)b->passes, b->counter, b->lds_max_n);
     else
         hipLaunchKernelGGL(k_batch<float>, dim3(b->grid), dim3(kBatchThreads), b->lds_bytes, b->stream,
                            (float2*)b->arena, (const BCirc*)b->circs, (const int32_t*)b->order,
-                           (uint32_t)b->count, (const BBlock*)b->blocks, (const BOp*)b->ops, b->counter,
-                           b->lds_max_n);
+                           (uint32_t)b->count, (const BBlock*)b->blocks, (const BOp*)b->ops,
+                           (const FPass*)b->passes, b->counter, b->lds_max_n);
     JQ_HIP(hipGetLastError());
 }
 
@@ -488,7 +607,9 @@ float timed_launch(jq_batch* b) {
 void autotune(jq_batch* b, const jq_exec_opts* opts) {
     std::vector<int> fixed(b->count, 0);
     if (opts && opts->fusion >= 1) {
-        for (size_t i = 0; i < b->count; ++i) b->kb[i] = std::min(opts->fusion, std::min(3, b->n[i]));
+        // depth 4 and up: tile mode where it applies (blocks of 3 elsewhere)
+        for (size_t i = 0; i < b->count; ++i)
+            b->kb[i] = opts->fusion >= kTileDepth ? kTileDepth : std::min(opts->fusion, std::min(3, b->n[i]));
         return;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -520,6 +641,20 @@ void autotune(jq_batch* b, const jq_exec_opts* opts) {
             best_ms = ms;
             for (int n : untuned) best[n] = std::min(k, n);
         }
+    }
+    // then tile mode for the sizes that allow it, the others at their best depth
+    bool any_tile = false;
+    for (int n : untuned) {
+        const bool t = tile_capable(b, n);
+        any_tile = any_tile || t;
+        for (size_t i : by_n[n]) b->kb[i] = t ? kTileDepth : best[n];
+    }
+    if (any_tile) {
+        upload_plans(b);
+        timed_launch(b);  // warm
+        if (timed_launch(b) < best_ms)
+            for (int n : untuned)
+                if (tile_capable(b, n)) best[n] = kTileDepth;
     }
     for (int n : untuned) {
         g_tuned_kb[{b->enc, n}] = best[n];

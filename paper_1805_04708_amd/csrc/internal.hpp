@@ -158,6 +158,9 @@ struct PlanConfig {
     // R register slots fixed to qubits 0..R-1; the F fixed lane bits are
     // then qubits R..R+F-1 (R = 0: lane bit b is qubit b)
     int fixed_reg_bits = 0;
+    // every run of fusable gates becomes a pass, however few bytes single
+    // gates would move (states that stay in the caches)
+    bool always_pass = false;
 };
 
 struct Plan {

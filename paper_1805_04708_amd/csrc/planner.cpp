@@ -415,7 +415,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
         rest.reserve(remaining.size());
         for (int i : remaining) if (!is_taken[i]) rest.push_back(i);
         remaining.swap(rest);
-        if (singles <= 1.0) {
+        if (!cfg.always_pass && singles <= 1.0) {
             for (int i : pb.taken) {
                 Step s;
                 s.op = ops[i];

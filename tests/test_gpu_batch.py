@@ -47,7 +47,7 @@ def oracle_state(n, circ):
 
 
 @pytest.mark.parametrize("enc,tol", [("c128", 1e-12), ("c64", 5e-6)])
-@pytest.mark.parametrize("fusion", [0, 1, 2, 3])
+@pytest.mark.parametrize("fusion", [0, 1, 2, 3, 4])
 def test_batch_matches_oracle(enc, tol, fusion):
     rng = np.random.default_rng(17 + fusion)
     inst = []
@@ -81,6 +81,39 @@ def test_batch_workload_sizes_and_alone_equality(enc):
         alone.run()
         assert np.array_equal(alone.amplitudes(i - i), first[i]), i
         alone.close()
+    b.close()
+
+
+@pytest.mark.parametrize("enc,tol", [("c128", 1e-12), ("c64", 5e-6)])
+def test_batch_tile_mode_large_states(enc, tol):
+    # states too large for LDS (N 13..16) in tile mode (depth 4): the
+    # planner's register/lane passes run by one workgroup per circuit; a
+    # circuit with a two-qubit dense gate (SWAP) falls back to blocks.  Every
+    # state against the oracle, and alone against in the batch, bit for bit
+    rng = np.random.default_rng(4)
+    inst = []
+    for i in range(24):
+        n = 13 + i % 4
+        circ = mixed_circuit(n, 60, rng)
+        if i % 6 != 0:
+            circ = [g for g in circ if g[0] != "SWAP"]
+        inst.append((n, circ))
+    b = jq.Batch(inst, enc, fusion=4)
+    b.run()
+    for i, (n, circ) in enumerate(inst):
+        got = b.amplitudes(i)
+        assert O.rel_l2(got, oracle_state(n, circ)) <= tol, (i, n)
+        if i % 5 == 0:
+            alone = jq.Batch([inst[i]], enc, fusion=4)
+            alone.run()
+            assert np.array_equal(alone.amplitudes(0), got), i
+            alone.close()
+    # the same circuits in block mode agree to rounding
+    blk = jq.Batch(inst, enc, fusion=3)
+    blk.run()
+    for i in range(len(inst)):
+        assert O.rel_l2(blk.amplitudes(i), b.amplitudes(i)) <= tol
+    blk.close()
     b.close()
 
 
