@@ -26,7 +26,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 # through chains of copy blocks)
 _UNIFORM = ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]
 PER_FILE = {"kernels_compact.hip": ["-ffp-contract=off"] + _UNIFORM,
-            "kernels_sv.hip": _UNIFORM}
+            "kernels_sv.hip": _UNIFORM, "batch.hip": _UNIFORM}
 
 
 def _sources():

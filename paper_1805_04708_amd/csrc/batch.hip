@@ -1,23 +1,27 @@
 // Batched small circuits in one persistent launch.
 //
-// Many independent circuits (each N <= 20) run in one kernel: a grid sized
-// to fill the GPU pulls circuit indices from a device work counter, largest
-// states first.  A workgroup owns one circuit at a time.  States of at most
+// Many independent circuits (each N <= 20) run as one batch: a grid sized to
+// fill the GPU pulls circuit indices from a device work counter, largest
+// states first, and a workgroup owns one circuit at a time.
+//
+// Block mode (fusion depth KB = 1..3): a circuit is cut into blocks of
+// consecutive gates whose targets fall in at most KB qubits.  For each block
+// every thread takes groups of 2^KB amplitudes (all values of the block's
+// qubits for one value of the others), applies all the block's gates in
+// registers, and writes them back; one barrier per block.  Diagonal gates
+// and controls are tested on each amplitude's full index.  States of at most
 // 64 KiB live in LDS for the whole circuit (two workgroups per CU); larger
 // ones are updated in place in their slot of the global arena, where they
 // stay L2/MALL resident.
 //
-// A circuit is cut into blocks of consecutive gates whose targets fall in
-// at most KB qubits (KB = the fusion depth, 1..3, tuned per encoding and N).
-// For each block every thread takes groups of 2^KB amplitudes (all values
-// of the block's qubits for one value of the others), applies all the
-// block's gates in registers, and writes them back; one barrier per block.
-// Diagonal gates and controls are tested on each amplitude's full index.
-//
-// Tile mode (depth 4, for states too large for LDS): the circuit runs as the
+// Tile mode (depth 4, states of at least one tile): the circuit runs as the
 // register/lane tile passes of the state-vector planner (many gates per
-// pass, reordered where they commute); the workgroup's waves loop over the
-// state's tiles, one barrier per pass.
+// pass, reordered where they commute) on its arena slot; the workgroup's
+// waves loop over the state's tiles, one barrier per pass.  Tile-mode
+// circuits run in their own kernel, without LDS, on a second stream forked
+// from the batch's stream, concurrently with the block-mode kernel.
+//
+// The depth is tuned per (encoding, N) on first use in the process.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -264,9 +268,12 @@ __device__ void run_block(typename Vec<R>::T* S, int n, const BBlock& blk, const
 // The passes of one circuit over its state psi (2^n amplitudes, in the
 // arena): each wave takes tiles wave, wave + 4, ...; the barrier after each
 // pass makes its stores visible to the next pass's loads (one workgroup, one
-// compute unit).
+// compute unit).  In batch plans a pass's ops field holds the index of its
+// first op in fops (a kernel argument, so the ops are read with scalar
+// loads).
 template <typename R>
-__device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* passes, int n_passes) {
+__device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* __restrict__ passes, int n_passes,
+                          const FOp* __restrict__ fops) {
     constexpr int K = TileShape<R>::K, F = TileShape<R>::F, S = 1 << K;
     const int lane = threadIdx.x & 63;
     const uint64_t wave = (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -280,7 +287,7 @@ __device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* passes, i
         uint64_t stride[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) stride[j] = 1ull << P.reg_q[j];
-        const FOp* ops = P.ops;
+        const FOp* ops = fops + reinterpret_cast<uintptr_t>(P.ops);
         const int n_ops = P.n_ops;
         for (uint64_t t = wave; t < ntiles; t += nw) {
             uint64_t base = tile_base(P, t, lane_off);
@@ -314,15 +321,16 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(typename Vec<R>::T* __r
                                                           const BCirc* __restrict__ circs,
                                                           const int32_t* __restrict__ order, uint32_t count,
                                                           const BBlock* __restrict__ blocks,
-                                                          const BOp* __restrict__ ops, const FPass* __restrict__ passes,
-                                                          uint32_t* counter, int lds_max_n) {
+                                                          const BOp* __restrict__ ops, uint32_t* counter,
+                                                          int lds_max_n) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     typename Vec<R>::T* lds = reinterpret_cast<typename Vec<R>::T*>(lds_raw);
     __shared__ uint32_t next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
         __syncthreads();
-        const uint32_t w = next;
+        // the same value in every lane: keep it (and what it indexes) scalar
+        const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)next);
         __syncthreads();
         if (w >= count) break;
         const BCirc c = circs[order[w]];
@@ -336,10 +344,6 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(typename Vec<R>::T* __r
             S[i] = v;
         }
         __syncthreads();
-        if (c.n_passes > 0) {
-            run_tiles<R>(S, n, passes + c.first_pass, c.n_passes);
-            continue;
-        }
         for (int b = 0; b < c.n_blocks; ++b) {
             const BBlock blk = blocks[c.first_block + b];
             switch (blk.k) {
@@ -356,8 +360,38 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(typename Vec<R>::T* __r
     }
 }
 
+// Tile-mode circuits (states in the arena): the same work counter scheme,
+// no LDS, so more workgroups fit per compute unit than in the block kernel.
+template <typename R>
+__global__ __launch_bounds__(kBatchThreads) void k_batch_tiles(typename Vec<R>::T* __restrict__ arena,
+                                                                const BCirc* __restrict__ circs,
+                                                                const int32_t* __restrict__ order, uint32_t count,
+                                                                const FPass* __restrict__ passes,
+                                                                const FOp* __restrict__ fops, uint32_t* counter) {
+    __shared__ uint32_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+        __syncthreads();
+        // the same value in every lane: keep it (and what it indexes) scalar
+        const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)next);
+        __syncthreads();
+        if (w >= count) break;
+        const BCirc c = circs[order[w]];
+        const uint32_t dim = 1u << c.n;
+        typename Vec<R>::T* S = arena + c.state_off;
+        for (uint32_t i = threadIdx.x; i < dim; i += blockDim.x) {
+            typename Vec<R>::T v;
+            v.x = (R)(i == 0 ? 1 : 0);
+            v.y = (R)0;
+            S[i] = v;
+        }
+        __syncthreads();
+        run_tiles<R>(S, c.n, passes + c.first_pass, c.n_passes, fops);
+    }
+}
+
 __global__ void k_batch_reset(uint32_t* counter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+    if (threadIdx.x < 2 && blockIdx.x == 0) counter[threadIdx.x] = 0u;
 }
 
 // ------------------------------------------------------------- host ------
@@ -472,7 +506,12 @@ struct jq_batch {
     uint64_t arena_amps = 0;
     void* arena = nullptr;
     void* circs = nullptr;
-    void* order = nullptr;
+    void* order = nullptr;       // block-mode circuits, largest state first
+    void* order_tile = nullptr;  // tile-mode circuits, largest state first
+    uint32_t count_blk = 0, count_tile = 0;
+    hipStream_t stream2 = nullptr;  // tile kernel, forked from stream
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int cus = 0, per_cu_blk = 1, per_cu_tile = 1;
     void* blocks = nullptr;
     void* ops = nullptr;
     void* passes = nullptr;  // tile mode: FPass per pass, ops pointing into fops
@@ -480,7 +519,6 @@ struct jq_batch {
     uint32_t* counter = nullptr;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    int grid = 0;
     int lds_max_n = 0;
     size_t lds_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -495,19 +533,22 @@ namespace {
 void free_batch(jq_batch* b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
-    for (void* p : {b->arena, b->circs, b->order, b->blocks, b->ops, b->passes, b->fops, (void*)b->counter})
+    if (b->stream2) (void)hipStreamSynchronize(b->stream2);
+    for (void* p : {b->arena, b->circs, b->order, b->order_tile, b->blocks, b->ops, b->passes, b->fops,
+                    (void*)b->counter})
         if (p) (void)hipFree(p);
-    if (b->ev0) (void)hipEventDestroy(b->ev0);
-    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    for (hipEvent_t e : {b->ev0, b->ev1, b->ev_fork, b->ev_join})
+        if (e) (void)hipEventDestroy(e);
+    if (b->stream2) (void)hipStreamDestroy(b->stream2);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
 
-// Tile mode applies to states in the arena (larger than LDS) that hold a
-// whole tile.
+// Tile mode applies to states that hold a whole tile (they then live in
+// the arena, not in LDS).
 bool tile_capable(const jq_batch* b, int n) {
     const int K = b->enc == JQ_C128 ? TileShape<double>::K : TileShape<float>::K;
-    return n > b->lds_max_n && n >= 6 + K;
+    return n >= 6 + K;
 }
 
 // The tile passes of one circuit (appended to passes/fops, ops pointers
@@ -526,7 +567,7 @@ bool plan_tiles(const jq_batch* b, size_t i, std::vector<FPass>& passes, std::ve
     const size_t base = fops.size();
     for (const Step& st : plan.steps) {
         FPass p = st.pass;
-        p.ops = reinterpret_cast<const FOp*>((uintptr_t)(base + st.first_fop));  // an index until upload
+        p.ops = reinterpret_cast<const FOp*>((uintptr_t)(base + st.first_fop));  // an index into fops
         passes.push_back(p);
     }
     fops.insert(fops.end(), plan.fops.begin(), plan.fops.end());
@@ -559,15 +600,28 @@ void upload_plans(jq_batch* b) {
     if (blocks.empty()) blocks.push_back(BBlock{});
     if (fops.empty()) fops.push_back(FOp{});
     if (passes.empty()) passes.push_back(FPass{});
-    for (void* p : {b->circs, b->blocks, b->ops, b->passes, b->fops})
+    // one work list per kernel, largest states first (the long jobs start early)
+    std::vector<int32_t> ob, ot;
+    for (size_t i = 0; i < b->count; ++i) (circs[i].n_passes > 0 ? ot : ob).push_back((int32_t)i);
+    auto larger = [&](int32_t x, int32_t y) { return b->n[x] > b->n[y]; };
+    std::stable_sort(ob.begin(), ob.end(), larger);
+    std::stable_sort(ot.begin(), ot.end(), larger);
+    b->count_blk = (uint32_t)ob.size();
+    b->count_tile = (uint32_t)ot.size();
+    if (ob.empty()) ob.push_back(0);
+    if (ot.empty()) ot.push_back(0);
+    for (void* p : {b->circs, b->blocks, b->ops, b->passes, b->fops, b->order, b->order_tile})
         if (p) JQ_HIP(hipFree(p));
-    b->circs = b->blocks = b->ops = b->passes = b->fops = nullptr;
+    b->circs = b->blocks = b->ops = b->passes = b->fops = b->order = b->order_tile = nullptr;
+    JQ_HIP(hipMalloc(&b->order, ob.size() * sizeof(int32_t)));
+    JQ_HIP(hipMalloc(&b->order_tile, ot.size() * sizeof(int32_t)));
+    JQ_HIP(hipMemcpy(b->order, ob.data(), ob.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    JQ_HIP(hipMemcpy(b->order_tile, ot.data(), ot.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     JQ_HIP(hipMalloc(&b->circs, circs.size() * sizeof(BCirc)));
     JQ_HIP(hipMalloc(&b->blocks, blocks.size() * sizeof(BBlock)));
     JQ_HIP(hipMalloc(&b->ops, bops.size() * sizeof(BOp)));
     JQ_HIP(hipMalloc(&b->fops, fops.size() * sizeof(FOp)));
     JQ_HIP(hipMalloc(&b->passes, passes.size() * sizeof(FPass)));
-    for (FPass& p : passes) p.ops = reinterpret_cast<const FOp*>(b->fops) + (uintptr_t)p.ops;
     JQ_HIP(hipMemcpy(b->circs, circs.data(), circs.size() * sizeof(BCirc), hipMemcpyHostToDevice));
     JQ_HIP(hipMemcpy(b->blocks, blocks.data(), blocks.size() * sizeof(BBlock), hipMemcpyHostToDevice));
     JQ_HIP(hipMemcpy(b->ops, bops.data(), bops.size() * sizeof(BOp), hipMemcpyHostToDevice));
@@ -577,17 +631,38 @@ void upload_plans(jq_batch* b) {
 
 void launch(jq_batch* b) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, b->counter);
-    if (b->enc == JQ_C128)
-        hipLaunchKernelGGL(k_batch<double>, dim3(b->grid), dim3(kBatchThreads), b->lds_bytes, b->stream,
-                           (double2*)b->arena, (const BCirc*)b->circs, (const int32_t*)b->order,
-                           (uint32_t)b->count, (const BBlock*)b->blocks, (const BOp*)b->ops,
-                           (const FPass*)b->passes, b->counter, b->lds_max_n);
-    else
-        hipLaunchKernelGGL(k_batch<float>, dim3(b->grid), dim3(kBatchThreads), b->lds_bytes, b->stream,
-                           (float2*)b->arena, (const BCirc*)b->circs, (const int32_t*)b->order,
-                           (uint32_t)b->count, (const BBlock*)b->blocks, (const BOp*)b->ops,
-                           (const FPass*)b->passes, b->counter, b->lds_max_n);
     JQ_HIP(hipGetLastError());
+    if (b->count_tile) {
+        // tile kernel on the second stream, concurrent with the block kernel
+        JQ_HIP(hipEventRecord(b->ev_fork, b->stream));
+        JQ_HIP(hipStreamWaitEvent(b->stream2, b->ev_fork, 0));
+        const unsigned grid = (unsigned)std::max(1, std::min<int>((int)b->count_tile, b->cus * b->per_cu_tile));
+        if (b->enc == JQ_C128)
+            hipLaunchKernelGGL(k_batch_tiles<double>, dim3(grid), dim3(kBatchThreads), 0, b->stream2,
+                               (double2*)b->arena, (const BCirc*)b->circs, (const int32_t*)b->order_tile,
+                               b->count_tile, (const FPass*)b->passes, (const FOp*)b->fops, b->counter + 1);
+        else
+            hipLaunchKernelGGL(k_batch_tiles<float>, dim3(grid), dim3(kBatchThreads), 0, b->stream2,
+                               (float2*)b->arena, (const BCirc*)b->circs, (const int32_t*)b->order_tile,
+                               b->count_tile, (const FPass*)b->passes, (const FOp*)b->fops, b->counter + 1);
+        JQ_HIP(hipGetLastError());
+        JQ_HIP(hipEventRecord(b->ev_join, b->stream2));
+    }
+    if (b->count_blk) {
+        const unsigned grid = (unsigned)std::max(1, std::min<int>((int)b->count_blk, b->cus * b->per_cu_blk));
+        if (b->enc == JQ_C128)
+            hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBatchThreads), b->lds_bytes, b->stream,
+                               (double2*)b->arena, (const BCirc*)b->circs, (const int32_t*)b->order,
+                               b->count_blk, (const BBlock*)b->blocks, (const BOp*)b->ops, b->counter,
+                               b->lds_max_n);
+        else
+            hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBatchThreads), b->lds_bytes, b->stream,
+                               (float2*)b->arena, (const BCirc*)b->circs, (const int32_t*)b->order,
+                               b->count_blk, (const BBlock*)b->blocks, (const BOp*)b->ops, b->counter,
+                               b->lds_max_n);
+        JQ_HIP(hipGetLastError());
+    }
+    if (b->count_tile) JQ_HIP(hipStreamWaitEvent(b->stream, b->ev_join, 0));
 }
 
 float timed_launch(jq_batch* b) {
@@ -642,19 +717,23 @@ void autotune(jq_batch* b, const jq_exec_opts* opts) {
             for (int n : untuned) best[n] = std::min(k, n);
         }
     }
-    // then tile mode for the sizes that allow it, the others at their best depth
-    bool any_tile = false;
-    for (int n : untuned) {
-        const bool t = tile_capable(b, n);
-        any_tile = any_tile || t;
-        for (size_t i : by_n[n]) b->kb[i] = t ? kTileDepth : best[n];
-    }
-    if (any_tile) {
+    // then tile mode, one size at a time from the largest down, kept where
+    // the whole batch gets faster
+    for (int n : untuned)
+        for (size_t i : by_n[n]) b->kb[i] = best[n];
+    for (auto it = untuned.rbegin(); it != untuned.rend(); ++it) {
+        const int n = *it;
+        if (!tile_capable(b, n)) continue;
+        for (size_t i : by_n[n]) b->kb[i] = kTileDepth;
         upload_plans(b);
         timed_launch(b);  // warm
-        if (timed_launch(b) < best_ms)
-            for (int n : untuned)
-                if (tile_capable(b, n)) best[n] = kTileDepth;
+        const float ms = timed_launch(b);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best[n] = kTileDepth;
+        } else {
+            for (size_t i : by_n[n]) b->kb[i] = best[n];
+        }
     }
     for (int n : untuned) {
         g_tuned_kb[{b->enc, n}] = best[n];
@@ -712,33 +791,31 @@ int jq_batch_create(const jq_circuit* cs, size_t count, jq_encoding enc, const j
         JQ_HIP(hipMemGetInfo(&free_b, &total_b));
         if (off * bpa > free_b) fail(JQ_ENOMEM, "jq_batch_create: arena does not fit in device memory");
         JQ_HIP(hipMalloc(&b->arena, off * bpa));
-        JQ_HIP(hipMalloc(&b->counter, sizeof(uint32_t)));
-        // largest states first: the long jobs start early
-        std::vector<int32_t> order(count);
-        for (size_t i = 0; i < count; ++i) order[i] = (int32_t)i;
-        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return b->n[x] > b->n[y]; });
-        JQ_HIP(hipMalloc(&b->order, count * sizeof(int32_t)));
-        JQ_HIP(hipMemcpy(b->order, order.data(), count * sizeof(int32_t), hipMemcpyHostToDevice));
+        JQ_HIP(hipMalloc(&b->counter, 2 * sizeof(uint32_t)));  // block kernel, tile kernel
         // LDS-resident states up to 64 KiB
         int lds_n = 0;
         while (lds_n < 20 && ((size_t)bpa << (lds_n + 1)) <= (size_t)kLdsBytes) ++lds_n;
         b->lds_max_n = lds_n;
         b->lds_bytes = (size_t)bpa << lds_n;
-        int dev = 0, cus = 0;
+        int dev = 0;
         JQ_HIP(hipGetDevice(&dev));
-        JQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        int per_cu = 0;
+        JQ_HIP(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev));
         const void* kfn = enc == JQ_C128 ? (const void*)k_batch<double> : (const void*)k_batch<float>;
+        const void* kft = enc == JQ_C128 ? (const void*)k_batch_tiles<double> : (const void*)k_batch_tiles<float>;
         JQ_HIP(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes));
-        JQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kBatchThreads, b->lds_bytes));
-        if (per_cu < 1) per_cu = 1;
-        b->grid = std::max(1, std::min<int>((int)count, cus * per_cu));
+        JQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->per_cu_blk, kfn, kBatchThreads, b->lds_bytes));
+        JQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->per_cu_tile, kft, kBatchThreads, 0));
+        b->per_cu_blk = std::max(1, b->per_cu_blk);
+        b->per_cu_tile = std::max(1, b->per_cu_tile);
         if (stream) {
             b->stream = (hipStream_t)stream;
         } else {
             JQ_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
             b->own_stream = true;
         }
+        JQ_HIP(hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking));
+        JQ_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+        JQ_HIP(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
         JQ_HIP(hipEventCreate(&b->ev0));
         JQ_HIP(hipEventCreate(&b->ev1));
         autotune(b, opts);
