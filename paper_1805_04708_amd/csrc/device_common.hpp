@@ -8,7 +8,6 @@
 namespace jq {
 
 constexpr int kBlock = 256;
-constexpr int kIt = 4;
 
 template <typename R>
 struct Vec;

@@ -9,7 +9,7 @@
 // a register/lane tile (see planner.cpp).  Reductions accumulate in FP64 in
 // a fixed order (per-thread sums, a fixed tree per block, then the block
 // partials in index order) so repeated calls give identical bits.
-#include "device_common.hpp"
+#include "fused_ops.hpp"
 
 namespace jq {
 
@@ -17,29 +17,44 @@ namespace jq {
 //
 // Blocks take chunks of IT * 256 groups (two-qubit: 2 * 256) and loop over
 // chunks when the grid is capped (a launch holds at most 2^32 threads).
+// Each amplitude is read and written once, so the accesses carry the
+// non-temporal hint, except where controls leave parts of each line
+// untouched.  IT is chosen per gate by the caller (measured at N=30
+// complex128: one pair per thread streams fastest for targets below 17,
+// four pairs above).
+template <typename R, bool NT>
+__device__ __forceinline__ Cx<R> ld_pg(const typename Vec<R>::T* p, uint64_t i) {
+    if constexpr (NT) return ld_stream<R>(p, i);
+    else return ld<R>(p, i);
+}
+template <typename R, bool NT>
+__device__ __forceinline__ void st_pg(typename Vec<R>::T* p, uint64_t i, Cx<R> a) {
+    if constexpr (NT) st_stream<R>(p, i, a);
+    else st<R>(p, i, a);
+}
 
-template <typename R>
+template <typename R, int IT, bool NT>
 __global__ __launch_bounds__(kBlock) void k_dense1(typename Vec<R>::T* __restrict__ psi, uint64_t ngroups,
                                                     Ins ins, uint64_t tbit, M4<R> m) {
-    for (uint64_t chunk = blockIdx.x; chunk * (kIt * kBlock) < ngroups; chunk += gridDim.x) {
-        const uint64_t g0 = chunk * (kIt * kBlock) + threadIdx.x;
-        uint64_t i0[kIt];
-        Cx<R> a[kIt], b[kIt];
+    for (uint64_t chunk = blockIdx.x; chunk * (IT * kBlock) < ngroups; chunk += gridDim.x) {
+        const uint64_t g0 = chunk * (IT * kBlock) + threadIdx.x;
+        uint64_t i0[IT];
+        Cx<R> a[IT], b[IT];
 #pragma unroll
-        for (int u = 0; u < kIt; ++u) {
+        for (int u = 0; u < IT; ++u) {
             const uint64_t g = g0 + (uint64_t)u * kBlock;
             if (g < ngroups) {
                 i0[u] = expand(g, ins);
-                a[u] = ld<R>(psi, i0[u]);
-                b[u] = ld<R>(psi, i0[u] | tbit);
+                a[u] = ld_pg<R, NT>(psi, i0[u]);
+                b[u] = ld_pg<R, NT>(psi, i0[u] | tbit);
             }
         }
 #pragma unroll
-        for (int u = 0; u < kIt; ++u) {
+        for (int u = 0; u < IT; ++u) {
             const uint64_t g = g0 + (uint64_t)u * kBlock;
             if (g < ngroups) {
-                st<R>(psi, i0[u], mac2(m.e[0], a[u], m.e[1], b[u]));
-                st<R>(psi, i0[u] | tbit, mac2(m.e[2], a[u], m.e[3], b[u]));
+                st_pg<R, NT>(psi, i0[u], mac2(m.e[0], a[u], m.e[1], b[u]));
+                st_pg<R, NT>(psi, i0[u] | tbit, mac2(m.e[2], a[u], m.e[3], b[u]));
             }
         }
     }
@@ -58,25 +73,25 @@ __global__ __launch_bounds__(kBlock) void k_dense2(typename Vec<R>::T* __restric
             const uint64_t idx[4] = {i, i | lbit, i | hbit, i | hbit | lbit};
             Cx<R> x[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) x[c] = ld<R>(psi, idx[c]);
+            for (int c = 0; c < 4; ++c) x[c] = ld_stream<R>(psi, idx[c]);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 Cx<R> s = cmul(m.e[4 * r], x[0]);
 #pragma unroll
                 for (int c = 1; c < 4; ++c) s = cadd(s, cmul(m.e[4 * r + c], x[c]));
-                st<R>(psi, idx[r], s);
+                st_stream<R>(psi, idx[r], s);
             }
         }
     }
 }
 
-template <typename R>
+template <typename R, int IT, bool NT>
 __global__ __launch_bounds__(kBlock) void k_diag(typename Vec<R>::T* __restrict__ psi, uint64_t ngroups,
                                                   Ins ins, int nsel, int s0, int s1, M4<R> d) {
-    for (uint64_t chunk = blockIdx.x; chunk * (kIt * kBlock) < ngroups; chunk += gridDim.x) {
-        const uint64_t g0 = chunk * (kIt * kBlock) + threadIdx.x;
+    for (uint64_t chunk = blockIdx.x; chunk * (IT * kBlock) < ngroups; chunk += gridDim.x) {
+        const uint64_t g0 = chunk * (IT * kBlock) + threadIdx.x;
 #pragma unroll
-        for (int u = 0; u < kIt; ++u) {
+        for (int u = 0; u < IT; ++u) {
             const uint64_t g = g0 + (uint64_t)u * kBlock;
             if (g >= ngroups) continue;
             const uint64_t i = expand(g, ins);
@@ -87,43 +102,38 @@ __global__ __launch_bounds__(kBlock) void k_diag(typename Vec<R>::T* __restrict_
             f = csel(sel == 1, d.e[1], f);
             f = csel(sel == 2, d.e[2], f);
             f = csel(sel == 3, d.e[3], f);
-            st<R>(psi, i, cmul(f, ld<R>(psi, i)));
+            st_pg<R, NT>(psi, i, cmul(f, ld_pg<R, NT>(psi, i)));
         }
     }
 }
 
-template <typename R>
+template <typename R, int IT, bool NT>
 __global__ __launch_bounds__(kBlock) void k_permx(typename Vec<R>::T* __restrict__ psi, uint64_t ngroups,
                                                    Ins ins, uint64_t tbit) {
-    for (uint64_t chunk = blockIdx.x; chunk * (kIt * kBlock) < ngroups; chunk += gridDim.x) {
-        const uint64_t g0 = chunk * (kIt * kBlock) + threadIdx.x;
-        uint64_t i0[kIt];
-        Cx<R> a[kIt], b[kIt];
+    for (uint64_t chunk = blockIdx.x; chunk * (IT * kBlock) < ngroups; chunk += gridDim.x) {
+        const uint64_t g0 = chunk * (IT * kBlock) + threadIdx.x;
+        uint64_t i0[IT];
+        Cx<R> a[IT], b[IT];
 #pragma unroll
-        for (int u = 0; u < kIt; ++u) {
+        for (int u = 0; u < IT; ++u) {
             const uint64_t g = g0 + (uint64_t)u * kBlock;
             if (g < ngroups) {
                 i0[u] = expand(g, ins);
-                a[u] = ld<R>(psi, i0[u]);
-                b[u] = ld<R>(psi, i0[u] | tbit);
+                a[u] = ld_pg<R, NT>(psi, i0[u]);
+                b[u] = ld_pg<R, NT>(psi, i0[u] | tbit);
             }
         }
 #pragma unroll
-        for (int u = 0; u < kIt; ++u) {
+        for (int u = 0; u < IT; ++u) {
             const uint64_t g = g0 + (uint64_t)u * kBlock;
             if (g < ngroups) {
-                st<R>(psi, i0[u], b[u]);
-                st<R>(psi, i0[u] | tbit, a[u]);
+                st_pg<R, NT>(psi, i0[u], b[u]);
+                st_pg<R, NT>(psi, i0[u] | tbit, a[u]);
             }
         }
     }
 }
 
-}  // namespace jq
-
-#include "fused_ops.hpp"
-
-namespace jq {
 
 // One tile per wavefront.
 template <typename R, int K, int F>
@@ -314,6 +324,18 @@ Ins make_ins(uint64_t zero_bits, uint64_t ones) {
 }
 
 // blocks for a per-gate kernel whose blocks loop over chunks of per_block
+// targets from this qubit up take four pairs per thread
+constexpr int kWideTarget = 17;
+
+// A control bit inside a 128-byte line (below qubit 3 for complex128, 4
+// for complex64) leaves parts of every line untouched: such gates keep
+// plain (cached) accesses, measured faster there than the streaming hint.
+template <typename R>
+bool partial_lines(uint64_t cmask) {
+    const uint64_t line_bits = sizeof(R) == 8 ? 3 : 4;
+    return (cmask & ((1ull << line_bits) - 1)) != 0;
+}
+
 unsigned chunk_blocks(uint64_t items, uint64_t per_block) {
     const uint64_t b = (items + per_block - 1) / per_block;
     return (unsigned)(b < 1 ? 1 : b < (1ull << 22) ? b : (1ull << 22));
@@ -342,8 +364,16 @@ void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, hipStream_t st
             const uint64_t ng = 1ull << (n - 1 - fixed);
             M4<R> m;
             for (int i = 0; i < 4; ++i) m.e[i] = {(R)op.m[i].re, (R)op.m[i].im};
-            hipLaunchKernelGGL(k_dense1<R>, dim3(chunk_blocks(ng, kIt * kBlock)), dim3(kBlock), 0, st, psi, ng,
-                               make_ins(op.cmask | tb, op.cmask), tb, m);
+            const Ins ins = make_ins(op.cmask | tb, op.cmask);
+            if (partial_lines<R>(op.cmask))
+                hipLaunchKernelGGL((k_dense1<R, 4, false>), dim3(chunk_blocks(ng, 4 * kBlock)), dim3(kBlock), 0, st,
+                                   psi, ng, ins, tb, m);
+            else if (op.t0 < kWideTarget)
+                hipLaunchKernelGGL((k_dense1<R, 1, true>), dim3(chunk_blocks(ng, kBlock)), dim3(kBlock), 0, st, psi,
+                                   ng, ins, tb, m);
+            else
+                hipLaunchKernelGGL((k_dense1<R, 4, true>), dim3(chunk_blocks(ng, 4 * kBlock)), dim3(kBlock), 0, st,
+                                   psi, ng, ins, tb, m);
             break;
         }
         case OP_DENSE2: {
@@ -359,16 +389,29 @@ void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, hipStream_t st
             const uint64_t ng = 1ull << (n - fixed);
             M4<R> d;
             for (int i = 0; i < 4; ++i) d.e[i] = {(R)op.m[i].re, (R)op.m[i].im};
-            hipLaunchKernelGGL(k_diag<R>, dim3(chunk_blocks(ng, kIt * kBlock)), dim3(kBlock), 0, st, psi, ng,
-                               make_ins(op.cmask, op.cmask), op.nsel, op.t0 < 0 ? 0 : op.t0,
-                               op.t1 < 0 ? 0 : op.t1, d);
+            const Ins ins = make_ins(op.cmask, op.cmask);
+            const int s0 = op.t0 < 0 ? 0 : op.t0, s1 = op.t1 < 0 ? 0 : op.t1;
+            if (partial_lines<R>(op.cmask))
+                hipLaunchKernelGGL((k_diag<R, 4, false>), dim3(chunk_blocks(ng, 4 * kBlock)), dim3(kBlock), 0, st,
+                                   psi, ng, ins, op.nsel, s0, s1, d);
+            else
+                hipLaunchKernelGGL((k_diag<R, 1, true>), dim3(chunk_blocks(ng, kBlock)), dim3(kBlock), 0, st, psi,
+                                   ng, ins, op.nsel, s0, s1, d);
             break;
         }
         case OP_PERMX: {
             const uint64_t tb = 1ull << op.t0;
             const uint64_t ng = 1ull << (n - 1 - fixed);
-            hipLaunchKernelGGL(k_permx<R>, dim3(chunk_blocks(ng, kIt * kBlock)), dim3(kBlock), 0, st, psi, ng,
-                               make_ins(op.cmask | tb, op.cmask), tb);
+            const Ins ins = make_ins(op.cmask | tb, op.cmask);
+            if (partial_lines<R>(op.cmask))
+                hipLaunchKernelGGL((k_permx<R, 4, false>), dim3(chunk_blocks(ng, 4 * kBlock)), dim3(kBlock), 0, st,
+                                   psi, ng, ins, tb);
+            else if (op.t0 < kWideTarget)
+                hipLaunchKernelGGL((k_permx<R, 1, true>), dim3(chunk_blocks(ng, kBlock)), dim3(kBlock), 0, st, psi,
+                                   ng, ins, tb);
+            else
+                hipLaunchKernelGGL((k_permx<R, 4, true>), dim3(chunk_blocks(ng, 4 * kBlock)), dim3(kBlock), 0, st,
+                                   psi, ng, ins, tb);
             break;
         }
         default:
