@@ -163,6 +163,31 @@ def test_invalid_gates_leave_state_untouched():
 # --------------------------------------------------------- circuits --
 
 @pytest.mark.parametrize("enc", ["c128", "c64"])
+def test_per_gate_kernel_variants_19_qubits(enc):
+    # one kernel per gate on a random 19-qubit state: dense and X targets
+    # below and above qubit 17 (one or four pairs per thread), controls
+    # inside a 128-byte line (plain accesses) and above it (streaming),
+    # diagonals with low and high bits, a Toffoli and a controlled dense gate
+    n = 19
+    rng = np.random.default_rng(19)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    circ = []
+    for t in (0, 2, 3, 9, 16, 17, 18):
+        circ.append(("MAT1", (t,), W.haar_u2(rng)))
+        circ.append(("X", (t,), ()))
+    circ += [("CNOT", (0, 18), ()), ("CNOT", (1, 17), ()), ("CNOT", (5, 18), ()), ("CNOT", (18, 3), ()),
+             ("MAT1", (17,), W.haar_u2(rng), (2,)), ("MAT1", (18,), W.haar_u2(rng), (12,)),
+             ("MAT1", (4,), W.haar_u2(rng), (0, 1)), ("TOFFOLI", (1, 2, 18), ()), ("TOFFOLI", (10, 11, 17), ()),
+             ("CZ", (0, 1), ()), ("CZ", (2, 3), ()), ("CZ", (5, 6), ()), ("CZ", (17, 18), ()),
+             ("CP", (0, 18), (0.7,)), ("RZ", (1,), (1.1,)), ("RZ", (18,), (2.3,)), ("T", (0,), ()),
+             ("S", (17,), ())]
+    got = run_gpu(n, enc, circ, fusion=1, init=psi0)
+    ref = run_oracle(n, circ, init=psi0)
+    assert O.rel_l2(got, ref) <= tol(enc, len(circ)), O.rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
 @pytest.mark.parametrize("fusion", [1, 0])
 def test_random_circuit_16_qubits(enc, fusion):
     # the 16-qubit, 200-gate random circuit workload
