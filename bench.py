@@ -290,7 +290,12 @@ def batch_extra(count=4096, seed=4096):
     inst = W.batch_instances(count, base_seed=seed)
     res = {"circuits": count, "gates_per_circuit": 100, "n_range": [8, 16]}
     for enc in ("c128", "c64"):
-        b = jq.Batch(inst, enc)
+        t0 = time.perf_counter()
+        b = jq.Batch(inst, enc)  # lowering, planning, first-use tuning, upload
+        create_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        jq.Batch(inst, enc).close()  # tuned: lowering, planning, upload
+        create_tuned_s = time.perf_counter() - t0
         b.run(timed=True)
         ms = min(b.run(timed=True) for _ in range(3))
         errs = []
@@ -299,7 +304,8 @@ def batch_extra(count=4096, seed=4096):
             ref = O.run(O.zero_state(n), n, circ)
             errs.append(O.rel_l2(b.amplitudes(i), ref))
         b.close()
-        res[enc] = {"circuits_per_s": count / (ms * 1e-3), "launch_ms": ms, "max_rel_l2_vs_oracle": max(errs),
+        res[enc] = {"circuits_per_s": count / (ms * 1e-3), "launch_ms": ms, "create_s_first": create_s,
+                    "create_s_tuned": create_tuned_s, "max_rel_l2_vs_oracle": max(errs),
                     "median_rel_l2_vs_oracle": float(np.median(errs)), "checked": len(errs)}
     return res
 

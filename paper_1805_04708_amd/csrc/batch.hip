@@ -524,6 +524,11 @@ struct jq_batch {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<std::vector<jq::GateOp>> ops_host;
     std::vector<int> kb;  // fusion depth used per circuit
+    // tile plans, made once per circuit on first use (0 = not made yet,
+    // 1 = made, -1 = the circuit cannot run in tile mode)
+    std::vector<int> tile_state;
+    std::vector<std::vector<jq::FPass>> tile_passes;  // ops field: index into tile_fops[i]
+    std::vector<std::vector<jq::FOp>> tile_fops;
 };
 
 namespace jq {
@@ -551,26 +556,38 @@ bool tile_capable(const jq_batch* b, int n) {
     return n >= 6 + K;
 }
 
-// The tile passes of one circuit (appended to passes/fops, ops pointers
-// holding fop indices until upload); false if some gate cannot run in a
-// pass (a two-qubit dense gate), in which case the circuit uses blocks.
-bool plan_tiles(const jq_batch* b, size_t i, std::vector<FPass>& passes, std::vector<FOp>& fops) {
-    PlanConfig cfg;
-    cfg.n = b->n[i];
-    cfg.fixed_lane_bits = b->enc == JQ_C128 ? TileShape<double>::F : TileShape<float>::F;
-    cfg.k_reg = b->enc == JQ_C128 ? TileShape<double>::K : TileShape<float>::K;
-    cfg.max_ops = 48;
-    cfg.always_pass = true;
-    Plan plan = make_plan(b->ops_host[i], cfg);
-    for (const Step& st : plan.steps)
-        if (!st.fused) return false;
-    const size_t base = fops.size();
-    for (const Step& st : plan.steps) {
-        FPass p = st.pass;
-        p.ops = reinterpret_cast<const FOp*>((uintptr_t)(base + st.first_fop));  // an index into fops
+// The tile passes of one circuit, appended to passes/fops (a pass's ops
+// field holds the index of its first op in fops); false if some gate cannot
+// run in a pass (a two-qubit dense gate), in which case the circuit uses
+// blocks.  The plan is made on first use and kept.
+bool plan_tiles(jq_batch* b, size_t i, std::vector<FPass>& passes, std::vector<FOp>& fops) {
+    if (b->tile_state[i] == 0) {
+        PlanConfig cfg;
+        cfg.n = b->n[i];
+        cfg.fixed_lane_bits = b->enc == JQ_C128 ? TileShape<double>::F : TileShape<float>::F;
+        cfg.k_reg = b->enc == JQ_C128 ? TileShape<double>::K : TileShape<float>::K;
+        cfg.max_ops = 48;
+        cfg.always_pass = true;
+        Plan plan = make_plan(b->ops_host[i], cfg);
+        bool ok = true;
+        for (const Step& st : plan.steps) ok = ok && st.fused;
+        b->tile_state[i] = ok ? 1 : -1;
+        if (ok) {
+            for (const Step& st : plan.steps) {
+                FPass p = st.pass;
+                p.ops = reinterpret_cast<const FOp*>((uintptr_t)st.first_fop);
+                b->tile_passes[i].push_back(p);
+            }
+            b->tile_fops[i] = std::move(plan.fops);
+        }
+    }
+    if (b->tile_state[i] < 0) return false;
+    const uintptr_t base = fops.size();
+    for (FPass p : b->tile_passes[i]) {
+        p.ops = reinterpret_cast<const FOp*>(base + reinterpret_cast<uintptr_t>(p.ops));
         passes.push_back(p);
     }
-    fops.insert(fops.end(), plan.fops.begin(), plan.fops.end());
+    fops.insert(fops.end(), b->tile_fops[i].begin(), b->tile_fops[i].end());
     return true;
 }
 
@@ -768,6 +785,9 @@ int jq_batch_create(const jq_circuit* cs, size_t count, jq_encoding enc, const j
         b->offs.resize(count);
         b->ops_host.resize(count);
         b->kb.assign(count, 2);
+        b->tile_state.assign(count, 0);
+        b->tile_passes.resize(count);
+        b->tile_fops.resize(count);
         uint64_t off = 0;
         for (size_t i = 0; i < count; ++i) {
             const int n = cs[i].n_qubits;
