@@ -96,7 +96,8 @@ enum FOpKind : int32_t {
     F_DIAG = 8,         // diagonal with one or two selector bits
     F_MDENSE_REG = 9,   // 2x2 on a register slot chosen by 1-2 selector bits
     F_MDENSE_LANE = 10, // 2x2 on a lane bit chosen by 1-2 selector bits
-    F_CSHIFT = 11,      // two-byte code: add the integer m[v] to the phase code (v = selector value)
+    F_CSHIFT = 11,      // two-byte code: add the integer m[v] to the phase code (v = selector value),
+                        // run as the masked-add terms cs_*
 };
 
 struct FOp {
