@@ -300,7 +300,7 @@ __device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* __restric
                     if (s & (1 << j)) off += stride[j];
                 a[s] = ld<R>(psi, base + off);
             }
-            run_ops<R, K>(a, ops, n_ops, base, lane);
+            run_ops<R, K>(a, ops, n_ops, base, wave_uniform(tile_base(P, t, 0)), lane);
             // recompute the store addresses instead of keeping 2^K of them live
             asm volatile("" : "+v"(base));
 #pragma unroll

@@ -39,11 +39,28 @@ __device__ __forceinline__ M2x2<R> msel(bool c, const M2x2<R>& x, const M2x2<R>&
 
 // A multiplexed op's selectors are thread index bits (lane or outer bits;
 // the planner never uses register slots for them): one matrix per thread.
+// An outer bit is the same in every lane of the wave (read from the tile
+// base ubase), so its part of the choice is made once for the wave, with
+// the matrix read by scalar loads; only lane-bit selectors choose per lane.
 template <typename R>
-__device__ __forceinline__ M2x2<R> mux_thread(const FOp* op, uint64_t base) {
-    const int g0 = (int)((base >> op->sel_glob[0]) & 1);
-    if (op->nsel == 1) return msel(g0 == 1, load_m_v<R>(op, 1), load_m_v<R>(op, 0));
-    const int v = 2 * g0 + (int)((base >> op->sel_glob[1]) & 1);
+__device__ __forceinline__ M2x2<R> mux_thread(const FOp* op, uint64_t base, uint64_t ubase) {
+    const int lm = op->sel_lane;
+    const int s0 = op->sel_glob[0];
+    if (op->nsel == 1) {
+        if (!(lm & 1)) return load_m_v<R>(op, (int)((ubase >> s0) & 1));
+        return msel(((base >> s0) & 1) != 0, load_m_v<R>(op, 1), load_m_v<R>(op, 0));
+    }
+    const int s1 = op->sel_glob[1];
+    if (!(lm & 3)) return load_m_v<R>(op, 2 * (int)((ubase >> s0) & 1) + (int)((ubase >> s1) & 1));
+    if (!(lm & 1)) {
+        const int v0 = 2 * (int)((ubase >> s0) & 1);
+        return msel(((base >> s1) & 1) != 0, load_m_v<R>(op, v0 + 1), load_m_v<R>(op, v0));
+    }
+    if (!(lm & 2)) {
+        const int v1 = (int)((ubase >> s1) & 1);
+        return msel(((base >> s0) & 1) != 0, load_m_v<R>(op, 2 + v1), load_m_v<R>(op, v1));
+    }
+    const int v = 2 * (int)((base >> s0) & 1) + (int)((base >> s1) & 1);
     M2x2<R> m = load_m_v<R>(op, 0);
     m = msel(v == 1, load_m_v<R>(op, 1), m);
     m = msel(v == 2, load_m_v<R>(op, 2), m);
@@ -53,8 +70,8 @@ __device__ __forceinline__ M2x2<R> mux_thread(const FOp* op, uint64_t base) {
 // Multiplexed 2x2 on register slot J: the matrix depends on 1-2 selector
 // bits (a diagonal gate folded into this one).
 template <typename R, int K, int J>
-__device__ __forceinline__ void reg_mdense(Cx<R> (&a)[1 << K], const FOp* op, uint64_t base) {
-    const M2x2<R> m = mux_thread<R>(op, base);
+__device__ __forceinline__ void reg_mdense(Cx<R> (&a)[1 << K], const FOp* op, uint64_t base, uint64_t ubase) {
+    const M2x2<R> m = mux_thread<R>(op, base, ubase);
 #pragma unroll
     for (int s = 0; s < (1 << K); ++s) {
         if (s & (1 << J)) continue;
@@ -151,7 +168,8 @@ __device__ __forceinline__ Cx<R> xor_lane_c(Cx<R> v) {
 // same register slot.  A lane with bit B = 0 computes row 0, one with bit
 // B = 1 row 1 (m11 x + m10 y with x its own, y the partner's value).
 template <typename R, int K, int B, int KIND>
-__device__ __forceinline__ void lane_op_b(Cx<R> (&a)[1 << K], const FOp* op, int lane, bool thr_ok, uint64_t base) {
+__device__ __forceinline__ void lane_op_b(Cx<R> (&a)[1 << K], const FOp* op, int lane, bool thr_ok, uint64_t base,
+                                          uint64_t ubase) {
     const uint32_t rc = op->reg_ctrl;
     if constexpr (KIND == F_PERM_LANE) {
 #pragma unroll
@@ -163,7 +181,7 @@ __device__ __forceinline__ void lane_op_b(Cx<R> (&a)[1 << K], const FOp* op, int
         }
     } else if constexpr (KIND == F_MDENSE_LANE) {
         const bool hi = (lane >> B) & 1;
-        const M2x2<R> m = mux_thread<R>(op, base);
+        const M2x2<R> m = mux_thread<R>(op, base, ubase);
         const Cx<R> cs = csel(hi, m.m3, m.m0), co = csel(hi, m.m2, m.m1);
 #pragma unroll
         for (int s = 0; s < (1 << K); ++s) {
@@ -235,22 +253,33 @@ __device__ __forceinline__ void phase_op(Cx<R> (&a)[1 << K], const FOp* op, bool
 // General diagonal: factor d[sel], sel from one or two selector bits that
 // are register slots (uniform per slot) or thread index bits.
 template <typename R, int K>
-__device__ __forceinline__ void diag_op(Cx<R> (&a)[1 << K], const FOp* op, uint64_t base, bool thr_ok) {
+__device__ __forceinline__ void diag_op(Cx<R> (&a)[1 << K], const FOp* op, uint64_t base, uint64_t ubase,
+                                        bool thr_ok) {
     Cx<R> d[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) d[i] = Cx<R>{(R)op->m[2 * i], (R)op->m[2 * i + 1]};
     const int nsel = op->nsel;
     const int r0 = op->sel_reg[0], r1 = op->sel_reg[1];
-    const int g0 = op->sel_glob[0] >= 0 ? (int)((base >> op->sel_glob[0]) & 1) : 0;
-    const int g1 = op->sel_glob[1] >= 0 ? (int)((base >> op->sel_glob[1]) & 1) : 0;
+    // a selector bit outside the lanes is the same in every lane: read it
+    // from the wave-uniform tile base
+    const int lm = op->sel_lane;
+    const int g0 = op->sel_glob[0] >= 0 ? (int)(((lm & 1 ? base : ubase) >> op->sel_glob[0]) & 1) : 0;
+    const int g1 = op->sel_glob[1] >= 0 ? (int)(((lm & 2 ? base : ubase) >> op->sel_glob[1]) & 1) : 0;
     const uint32_t rc = op->reg_ctrl;
     if (r0 < 0 && r1 < 0) {
         // every selector is a thread index bit: one factor per thread
-        const int sel = nsel == 1 ? g0 : 2 * g0 + g1;
-        Cx<R> f = d[0];
-        f = csel(sel == 1, d[1], f);
-        f = csel(sel == 2, d[2], f);
-        f = csel(sel == 3, d[3], f);
+        Cx<R> f;
+        if (!(lm & 3)) {
+            // no lane selector: the factor is the same in every lane
+            const int sel = nsel == 1 ? g0 : 2 * g0 + g1;
+            f = Cx<R>{(R)op->m[2 * sel], (R)op->m[2 * sel + 1]};
+        } else {
+            const int sel = nsel == 1 ? g0 : 2 * g0 + g1;
+            f = d[0];
+            f = csel(sel == 1, d[1], f);
+            f = csel(sel == 2, d[2], f);
+            f = csel(sel == 3, d[3], f);
+        }
         f = csel(thr_ok, f, Cx<R>{(R)1, (R)0});
         if (rc == 0) {
 #pragma unroll
@@ -284,7 +313,8 @@ __device__ __forceinline__ void diag_op(Cx<R> (&a)[1 << K], const FOp* op, uint6
 }
 
 template <typename R, int K, int KIND>
-__device__ __forceinline__ void reg_dispatch(Cx<R> (&a)[1 << K], const FOp* op, bool thr_ok, uint64_t base) {
+__device__ __forceinline__ void reg_dispatch(Cx<R> (&a)[1 << K], const FOp* op, bool thr_ok, uint64_t base,
+                                             uint64_t ubase) {
     switch (op->slot) {
 #define JQ_CASE(J)                                                                       \
     case J:                                                                              \
@@ -292,7 +322,7 @@ __device__ __forceinline__ void reg_dispatch(Cx<R> (&a)[1 << K], const FOp* op, 
                                                             \
             if constexpr (KIND == F_DENSE_REG) reg_dense<R, K, J, false>(a, op, thr_ok); \
             else if constexpr (KIND == F_CDENSE_REG) reg_dense<R, K, J, true>(a, op, thr_ok); \
-            else if constexpr (KIND == F_MDENSE_REG) reg_mdense<R, K, J>(a, op, base);   \
+            else if constexpr (KIND == F_MDENSE_REG) reg_mdense<R, K, J>(a, op, base, ubase); \
             else reg_perm<R, K, J>(a, op, thr_ok);                                       \
         }                                                                                \
         break;
@@ -310,12 +340,12 @@ __device__ __forceinline__ void reg_dispatch(Cx<R> (&a)[1 << K], const FOp* op, 
 
 template <typename R, int K, int KIND>
 __device__ __forceinline__ void lane_dispatch(Cx<R> (&a)[1 << K], const FOp* op, int lane, bool thr_ok,
-                                              uint64_t base = 0) {
+                                              uint64_t base = 0, uint64_t ubase = 0) {
     switch (op->slot) {
 #define JQ_LCASE(B)                                             \
     case B:                                                     \
                                   \
-        lane_op_b<R, K, B, KIND>(a, op, lane, thr_ok, base);    \
+        lane_op_b<R, K, B, KIND>(a, op, lane, thr_ok, base, ubase); \
         break;
         JQ_LCASE(0)
         JQ_LCASE(1)
@@ -368,21 +398,23 @@ __device__ __forceinline__ void st_stream(typename Vec<R>::T* p, uint64_t i, Cx<
 #endif
 }
 
+// base: index of the lane's first amplitude; ubase: the tile's base, the
+// same in every lane (base without the lane bits)
 template <typename R, int K>
 __device__ __forceinline__ void run_ops(Cx<R> (&a)[1 << K], const FOp* __restrict__ ops, int n_ops, uint64_t base,
-                                        int lane) {
+                                        uint64_t ubase, int lane) {
     for (int k = 0; k < n_ops; ++k) {
         const FOp* op = ops + k;
         const bool thr_ok = (base & op->thr_ctrl) == op->thr_ctrl;
         switch (op->kind) {
             case F_DENSE_REG:
-                reg_dispatch<R, K, F_DENSE_REG>(a, op, thr_ok, base);
+                reg_dispatch<R, K, F_DENSE_REG>(a, op, thr_ok, base, ubase);
                 break;
             case F_CDENSE_REG:
-                reg_dispatch<R, K, F_CDENSE_REG>(a, op, thr_ok, base);
+                reg_dispatch<R, K, F_CDENSE_REG>(a, op, thr_ok, base, ubase);
                 break;
             case F_PERM_REG:
-                reg_dispatch<R, K, F_PERM_REG>(a, op, thr_ok, base);
+                reg_dispatch<R, K, F_PERM_REG>(a, op, thr_ok, base, ubase);
                 break;
             case F_DENSE_LANE:
                 lane_dispatch<R, K, F_DENSE_LANE>(a, op, lane, thr_ok);
@@ -394,10 +426,10 @@ __device__ __forceinline__ void run_ops(Cx<R> (&a)[1 << K], const FOp* __restric
                 lane_dispatch<R, K, F_PERM_LANE>(a, op, lane, thr_ok);
                 break;
             case F_MDENSE_REG:
-                reg_dispatch<R, K, F_MDENSE_REG>(a, op, thr_ok, base);
+                reg_dispatch<R, K, F_MDENSE_REG>(a, op, thr_ok, base, ubase);
                 break;
             case F_MDENSE_LANE:
-                lane_dispatch<R, K, F_MDENSE_LANE>(a, op, lane, thr_ok, base);
+                lane_dispatch<R, K, F_MDENSE_LANE>(a, op, lane, thr_ok, base, ubase);
                 break;
             case F_PHASE:
                 phase_op<R, K, false>(a, op, thr_ok);
@@ -406,12 +438,19 @@ __device__ __forceinline__ void run_ops(Cx<R> (&a)[1 << K], const FOp* __restric
                 phase_op<R, K, true>(a, op, thr_ok);
                 break;
             case F_DIAG:
-                diag_op<R, K>(a, op, base, thr_ok);
+                diag_op<R, K>(a, op, base, ubase, thr_ok);
                 break;
             default:
                 break;
         }
     }
+}
+
+// A 64-bit value that is the same in every lane, held in scalar registers
+// (readfirstlane returns int: each half goes through uint32_t).
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t x) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32)) << 32) |
+           (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
 }
 
 // Index of lane `lane`'s first amplitude in tile w: the tile number fills

@@ -109,7 +109,8 @@ struct FOp {
     int32_t sel_reg[2];  // diag selector / dense multiplexer bit as register slot, or -1
     int32_t sel_glob[2]; // the same as a thread index bit (lane/outer), or -1
     int32_t nsel;        // diag: selector bits; dense: multiplexer bits (0..2)
-    int32_t pad;
+    int32_t sel_lane;    // bit i: sel_glob[i] is a lane bit of the tile (else an
+                         // outer bit, the same in every lane of a wave)
     // dense: matrix v (v = multiplexer value, first selector the MSB) at
     // m[8v .. 8v+7] as m00 m01 m10 m11; diag: d0..d3
     double m[32];

@@ -624,7 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_cp_fused(int8_t* __restrict__ b0, in
                 if (s & (1 << j)) off += stride[j];
             a[s] = decode_tab(tab, b0[base + off], b1[base + off]);
         }
-        run_ops<double, K>(a, ops, P.n_ops, base, lane);
+        run_ops<double, K>(a, ops, P.n_ops, base, wave_uniform(tile_base(P, w, 0)), lane);
         // recompute the store addresses instead of keeping 2^K of them live
         uint64_t sbase = base;
         asm volatile("" : "+v"(sbase));
@@ -864,11 +864,7 @@ __global__ __launch_bounds__(kBlock) void k_cp_codes(int8_t* __restrict__ b0, in
 #pragma unroll
     for (int j = 0; j < K; ++j) stride[j] = 1ull << P.reg_q[j];
     for (uint64_t w = wave0; w < ntiles; w += nwaves) {
-    const uint64_t t0 = tile_base(P, w, 0);
-    // readfirstlane returns int: each half goes through uint32_t so the low
-    // half is not sign-extended into the high one
-    const uint64_t ubase = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(t0 >> 32)) << 32) |
-                           (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)t0);
+    const uint64_t ubase = wave_uniform(tile_base(P, w, 0));
     const uint64_t base = ubase | (uint64_t)lane_b;
     uint32_t c[NP];
 #pragma unroll

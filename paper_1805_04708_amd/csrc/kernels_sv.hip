@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(typename Vec<R>::T* __restrict
             if (s & (1 << j)) off += stride[j];
         a[s] = ld_stream<R>(psi, base + off);
     }
-    run_ops<R, K>(a, ops, P.n_ops, base, lane);
+    run_ops<R, K>(a, ops, P.n_ops, base, wave_uniform(tile_base(P, wave, 0)), lane);
     // recompute the store addresses instead of keeping 2^K of them live
     asm volatile("" : "+v"(base));
 #pragma unroll

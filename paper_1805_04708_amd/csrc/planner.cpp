@@ -113,6 +113,7 @@ FOp lower_fop(const GateOp& op, const FPass& p, int F, int K, int nmux = 0, cons
                 int jr = reg_of(mux[i]);
                 if (jr >= 0) f.sel_reg[i] = jr;
                 else f.sel_glob[i] = mux[i];
+                if (jr < 0 && lane_of(mux[i]) >= 0) f.sel_lane |= 1 << i;
             }
             for (int v = 0; v < (1 << nmux); v++)
                 for (int i = 0; i < 4; i++) {
@@ -178,6 +179,7 @@ FOp lower_fop(const GateOp& op, const FPass& p, int F, int K, int nmux = 0, cons
             int j = reg_of(sel[i]);
             if (j >= 0) f.sel_reg[i] = j;
             else f.sel_glob[i] = sel[i];
+            if (j < 0 && lane_of(sel[i]) >= 0) f.sel_lane |= 1 << i;
         }
         for (int i = 0; i < 4; i++) {
             f.m[2 * i] = op.m[i].re;
