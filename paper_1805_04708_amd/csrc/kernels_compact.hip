@@ -705,7 +705,16 @@ __device__ __forceinline__ void hc_perm_reg(uint32_t (&c)[P], uint32_t rc, bool 
     constexpr int B = 1 << (J - 1);
     if constexpr (B < P) {
         const uint32_t rr = rc >> 1;
-        if (!(rc & 1u)) {
+        if (rc == 0) {
+            // no control in the slots: one condition for the whole thread
+#pragma unroll
+            for (int r = 0; r < P; ++r) {
+                if (r & B) continue;
+                const uint32_t x = c[r], y = c[r | B];
+                c[r] = thr_ok ? y : x;
+                c[r | B] = thr_ok ? x : y;
+            }
+        } else if (!(rc & 1u)) {
 #pragma unroll
             for (int r = 0; r < P; ++r) {
                 if (r & B) continue;
@@ -732,6 +741,11 @@ __device__ __forceinline__ void hc_perm_reg(uint32_t (&c)[P], uint32_t rc, bool 
 template <int P>
 __device__ __forceinline__ void hc_perm_half(uint32_t (&c)[P], uint32_t rc, bool thr_ok) {
     const uint32_t rr = rc >> 1;
+    if (rr == 0) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) c[r] = thr_ok ? swap_halves(c[r]) : c[r];
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < P; ++r) {
         const bool ok = thr_ok && ((uint32_t)r & rr) == rr;
@@ -763,13 +777,22 @@ template <int P>
 __device__ __forceinline__ void hc_perm_lane(uint32_t (&c)[P], int b, uint32_t rc, bool thr_ok) {
     const int mask = 1 << b;
     const uint32_t rr = rc >> 1;
+    if (rc == 0) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const uint32_t partner = (uint32_t)__shfl_xor((int)c[r], mask, 64);
+            c[r] = thr_ok ? partner : c[r];
+            // a few exchanges in flight at a time, not one result register per slot
+            if ((r & 7) == 7) JQ_SLOT_FENCE();
+        }
+        return;
+    }
     const uint32_t keep = (rc & 1u) ? 0x0000ffffu : 0u;
 #pragma unroll
     for (int r = 0; r < P; ++r) {
         const uint32_t partner = (uint32_t)__shfl_xor((int)c[r], mask, 64);
         const bool ok = thr_ok && ((uint32_t)r & rr) == rr;
         c[r] = ok ? (partner & ~keep) | (c[r] & keep) : c[r];
-        // a few exchanges in flight at a time, not one result register per slot
         if ((r & 7) == 7) JQ_SLOT_FENCE();
     }
 }
