@@ -50,11 +50,32 @@ double touched_fraction(const GateOp& op, int n) {
     return std::ldexp((double)op.touched(n), -n);
 }
 
-// Can the op run inside a fused pass?  Two-qubit dense ops never do; on the
-// two-byte code with per-gate quantisation only the ops that are exact on
-// the codes do: permutations and phase shifts by a non-tie integer.
+// A SWAP (controls allowed): the two-qubit dense op whose matrix exchanges
+// |01> and |10>.  It is a permutation, so it runs in a pass as three
+// controlled X ops (exact on the two-byte code too).
+bool is_swap(const GateOp& op) {
+    if (op.kind != OP_DENSE2) return false;
+    for (int i = 0; i < 16; ++i) {
+        const double want = (i == 0 || i == 6 || i == 9 || i == 15) ? 1.0 : 0.0;
+        if (op.m[i].re != want || op.m[i].im != 0.0) return false;
+    }
+    return true;
+}
+
+// Index bits whose values an op changes (none for a diagonal op).
+uint64_t changed_bits(const GateOp& op) {
+    if (op.kind == OP_DIAG) return 0;
+    uint64_t t = 1ull << op.t0;
+    if (op.kind == OP_DENSE2) t |= 1ull << op.t1;
+    return t;
+}
+
+// Can the op run inside a fused pass?  Two-qubit dense ops other than SWAP
+// never do; on the two-byte code with per-gate quantisation only the ops
+// that are exact on the codes do: permutations (SWAP included) and phase
+// shifts by a non-tie integer.
 bool fusable(const GateOp& op, const PlanConfig& cfg) {
-    if (op.kind == OP_DENSE2) return false;
+    if (op.kind == OP_DENSE2) return is_swap(op);
     if (!cfg.code_domain) return true;
     if (op.kind == OP_PERMX) return true;
     double d[4];
@@ -67,6 +88,9 @@ bool fusable(const GateOp& op, const PlanConfig& cfg) {
 // shift reads the modulus plane and reads and writes the phase plane).
 double single_cost(const GateOp& op, const PlanConfig& cfg) {
     const double t = touched_fraction(op, cfg.n);
+    // a SWAP alone runs the two-qubit dense kernel (the two-byte code:
+    // decode, 4x4 product, encode), which costs more than a pass
+    if (is_swap(op)) return 2.0 * t;
     if (!cfg.code_domain) return t;
     return op.kind == OP_PERMX ? t : 0.75 * t;
 }
@@ -267,14 +291,14 @@ void absorb_diagonals(std::vector<PassOp>& ops, uint64_t reg_bits) {
         for (size_t j = i + 1; j < ops.size() && !done; ++j) {
             PassOp& u = ops[j];
             if (!u.alive || u.op.kind == OP_DIAG) continue;
-            if (!(q & (1ull << u.op.t0))) continue;
+            if (!(q & changed_bits(u.op))) continue;
             if (absorbable(u) && absorb(u, d, true, reg_bits)) done = true;
             break;
         }
         for (size_t j = i; j-- > 0 && !done;) {
             PassOp& u = ops[j];
             if (!u.alive || u.op.kind == OP_DIAG) continue;
-            if (!(q & (1ull << u.op.t0))) continue;
+            if (!(q & changed_bits(u.op))) continue;
             if (absorbable(u) && absorb(u, d, false, reg_bits)) done = true;
             break;
         }
@@ -344,7 +368,7 @@ void merge_same_target(std::vector<PassOp>& ops) {
                 break;
             }
             if (involved(c) & tb) break;
-            if (c.op.kind != OP_DIAG && (sa & (1ull << c.op.t0))) break;
+            if (sa & changed_bits(c.op)) break;
         }
     }
 }
@@ -388,7 +412,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
                 ok = false;  // two-qubit dense blocks run unfused
             } else if (!diag) {
                 PassBuilder trial = pb;
-                ok = trial.place(op.t0);
+                ok = trial.place(op.t0) && (op.kind != OP_DENSE2 || trial.place(op.t1));
                 if (ok) pb = trial;
             }
             if (!ok) {
@@ -465,6 +489,23 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
         int n_ops = 0;
         for (auto& po : pops) {
             if (!po.alive) continue;
+            if (is_swap(po.op)) {
+                // SWAP(a, b) = X on b where a = 1, X on a where b = 1, X on b
+                // where a = 1 (each with the SWAP's own controls as well)
+                const int a = po.op.t0, b = po.op.t1;
+                GateOp xb;
+                xb.kind = OP_PERMX;
+                xb.t0 = b;
+                xb.cmask = po.op.cmask | (1ull << a);
+                xb.keeps_modulus = true;
+                GateOp xa = xb;
+                xa.t0 = a;
+                xa.cmask = po.op.cmask | (1ull << b);
+                for (const GateOp* x : {&xb, &xa, &xb})
+                    plan.fops.push_back(lower_fop(*x, p, F, K, 0, nullptr, nullptr, cfg.code_domain));
+                n_ops += 3;
+                continue;
+            }
             // a diagonal on the target alone folds into the matrix itself
             if (po.op.kind == OP_DENSE1 && po.nsel == 0)
                 for (int e = 0; e < 4; ++e) po.op.m[e] = po.mats[0][e];

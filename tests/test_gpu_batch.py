@@ -87,16 +87,19 @@ def test_batch_workload_sizes_and_alone_equality(enc):
 @pytest.mark.parametrize("enc,tol", [("c128", 1e-12), ("c64", 5e-6)])
 def test_batch_tile_mode_large_states(enc, tol):
     # states too large for LDS (N 13..16) in tile mode (depth 4): the
-    # planner's register/lane passes run by one workgroup per circuit; a
-    # circuit with a two-qubit dense gate (SWAP) falls back to blocks.  Every
-    # state against the oracle, and alone against in the batch, bit for bit
+    # planner's register/lane passes run by one workgroup per circuit (SWAPs
+    # included); a circuit with a general two-qubit dense gate falls back to
+    # blocks.  Every state against the oracle, and alone against in the
+    # batch, bit for bit
     rng = np.random.default_rng(4)
     inst = []
     for i in range(24):
         n = 13 + i % 4
         circ = mixed_circuit(n, 60, rng)
-        if i % 6 != 0:
-            circ = [g for g in circ if g[0] != "SWAP"]
+        if i % 6 == 0:
+            q, _ = np.linalg.qr(rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4)))
+            flat = [float(v) for x in q.ravel() for v in (x.real, x.imag)]
+            circ.insert(30, ("MAT2", (1, n - 1), tuple(flat)))
         inst.append((n, circ))
     b = jq.Batch(inst, enc, fusion=4)
     b.run()

@@ -57,11 +57,12 @@ def test_controls_ties_and_every_code_op():
     circ = [("H", (q,), ()) for q in range(n)]
     for _ in range(120):
         q = [int(x) for x in rng.permutation(n)[:4]]
-        kind = int(rng.integers(10))
+        kind = int(rng.integers(12))
         circ.append([("X", (q[0],), ()), ("CNOT", (q[0], q[1]), ()), ("TOFFOLI", (q[0], q[1], q[2]), ()),
                      ("X", (q[0],), (), (q[1], q[2], q[3])), ("Z", (q[0],), ()), ("S", (q[0],), ()),
                      ("T+", (q[0],), ()), ("CZ", (q[0], q[1]), ()), ("R", (q[0],), (int(rng.integers(1, 11)),)),
-                     ("U", (q[0], q[1]), (int(rng.integers(1, 11)),))][kind])
+                     ("U", (q[0], q[1]), (int(rng.integers(1, 11)),)), ("SWAP", (q[0], q[1]), ()),
+                     ("SWAP", (q[0], q[1]), (), (q[2],))][kind])
     # random codes (canonical: zero amplitudes carry phase code 0)
     b0 = rng.integers(-127, 127, 1 << n).astype(np.int8)
     b1 = rng.integers(-128, 128, 1 << n).astype(np.int8)

@@ -162,6 +162,37 @@ def test_invalid_gates_leave_state_untouched():
 
 # --------------------------------------------------------- circuits --
 
+def random_u4(rng):
+    q, _ = np.linalg.qr(rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4)))
+    flat = []
+    for x in q.ravel():
+        flat += [float(x.real), float(x.imag)]
+    return tuple(flat)
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+@pytest.mark.parametrize("fusion", [0, 2, 3, 4, 5])
+def test_swap_in_fused_passes(enc, fusion):
+    # SWAPs (some controlled) run inside passes as three controlled X ops,
+    # with diagonal gates on their qubits before and after (which must not
+    # move past them) and a general two-qubit gate that stays unfused
+    n = 13
+    rng = np.random.default_rng(100 + fusion)
+    circ = [("H", (q,), ()) for q in range(n)]
+    for _ in range(60):
+        a, b, c = (int(x) for x in rng.permutation(n)[:3])
+        circ += [("CP", (a, c), (float(rng.uniform(-3, 3)),)), ("RZ", (b,), (float(rng.uniform(0, 6)),)),
+                 ("SWAP", (a, b), ()) if rng.random() < 0.7 else ("SWAP", (a, b), (), (c,)),
+                 ("T", (a,), ()), ("CZ", (b, c), ()), ("MAT1", (a,), W.haar_u2(rng))]
+        if rng.random() < 0.1:
+            circ.append(("MAT2", (a, c), random_u4(rng)))
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    got = run_gpu(n, enc, circ, fusion=fusion, init=psi0)
+    ref = run_oracle(n, circ, init=psi0)
+    assert O.rel_l2(got, ref) <= tol(enc, len(circ)), O.rel_l2(got, ref)
+
+
 @pytest.mark.parametrize("enc", ["c128", "c64"])
 def test_per_gate_kernel_variants_19_qubits(enc):
     # one kernel per gate on a random 19-qubit state: dense and X targets

@@ -81,9 +81,39 @@ def test_fused_blocks_fit_one_tile(enc, kw):
             n_fused += 1
             free = {q for g in blk for q in targets_of(g)} - set(range(F))
             assert len(free) <= (6 - F) + K, (enc, sorted(free))
-            assert all(len(g[1]) - (1 if g[0] == "CNOT" else 2 if g[0] == "TOFFOLI" else 0) <= 1 or
-                       not targets_of(g) for g in blk), "two-qubit dense gates run unfused"
+            # two-qubit dense gates other than SWAP (a permutation: three
+            # controlled X ops in the pass) run unfused
+            assert all(g[0] == "SWAP" or len(g[1]) - (1 if g[0] == "CNOT" else 2 if g[0] == "TOFFOLI" else 0) <= 1
+                       or not targets_of(g) for g in blk), "two-qubit dense gates run unfused"
         assert n_fused > 0
+
+
+def test_swap_fuses_and_general_two_qubit_gates_do_not():
+    # the QFT's closing SWAPs join passes; a general 4x4 runs alone
+    n = 14
+    rng = np.random.default_rng(3)
+    circ = W.qft(n)
+    q, r = np.linalg.qr(rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4)))
+    flat = []
+    for x in q.ravel():
+        flat += [float(x.real), float(x.imag)]
+    circ = circ[:40] + [("MAT2", (2, 9), tuple(flat))] + circ[40:]
+    for enc, kw in [("c128", {}), ("c64", {}), ("compact", {"compact_mode": PER_BLOCK}), ("compact", {})]:
+        order, blen, fused = schedule(n, enc, circ, **kw)
+        where_fused = {}
+        pos = 0
+        for b, f in zip(blen, fused):
+            for i in order[pos:pos + b]:
+                where_fused[i] = bool(f)
+            pos += b
+        swaps = [i for i, g in enumerate(circ) if g[0] == "SWAP"]
+        assert swaps and all(where_fused[i] for i in swaps), (enc, kw)
+        mat2 = [i for i, g in enumerate(circ) if g[0] == "MAT2"][0]
+        assert not where_fused[mat2]
+        # the reordered circuit is the same unitary
+        psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+        psi /= np.linalg.norm(psi)
+        assert O.rel_l2(O.run(psi.copy(), n, [circ[i] for i in order]), O.run(psi.copy(), n, circ)) < 1e-13
 
 
 def test_unfused_modes_keep_the_input_order():
