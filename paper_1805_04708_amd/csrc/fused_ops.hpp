@@ -297,6 +297,23 @@ __device__ __forceinline__ void diag_op(Cx<R> (&a)[1 << K], const FOp* op, uint6
         }
         return;
     }
+    if (!op->has_ctrl && !(lm & 3)) {
+        // no controls and no lane selector: every factor is chosen per slot,
+        // the same in every lane (an RZ on a register qubit, say)
+#pragma unroll
+        for (int s = 0; s < (1 << K); ++s) {
+            const int b0 = r0 >= 0 ? ((s >> r0) & 1) : g0;
+            const int b1 = r1 >= 0 ? ((s >> r1) & 1) : g1;
+            const int sel = nsel == 1 ? b0 : 2 * b0 + b1;
+            Cx<R> f = d[0];
+            f = csel(sel == 1, d[1], f);
+            f = csel(sel == 2, d[2], f);
+            f = csel(sel == 3, d[3], f);
+            a[s] = cmulf(f, a[s]);
+            JQ_SLOT_FENCE();
+        }
+        return;
+    }
 #pragma unroll
     for (int s = 0; s < (1 << K); ++s) {
         const int b0 = r0 >= 0 ? ((s >> r0) & 1) : g0;
