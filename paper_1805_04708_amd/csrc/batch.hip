@@ -697,7 +697,6 @@ float timed_launch(jq_batch* b) {
 // state up to rounding) and keeps the fastest for the rest of the process,
 // so a circuit runs the same code in every batch of this process.
 void autotune(jq_batch* b, const jq_exec_opts* opts) {
-    std::vector<int> fixed(b->count, 0);
     if (opts && opts->fusion >= 1) {
         // depth 4 and up: tile mode where it applies (blocks of 3 elsewhere)
         for (size_t i = 0; i < b->count; ++i)
@@ -718,9 +717,7 @@ void autotune(jq_batch* b, const jq_exec_opts* opts) {
     if (untuned.empty()) return;
     // time each depth on the whole batch with the untuned sizes at that depth
     const int maxk = 3;
-    std::map<int, std::vector<float>> cost;  // n -> per-depth time share
     float best_ms = 0;
-    std::vector<int> saved = b->kb;
     std::map<int, int> best;
     for (int n : untuned) best[n] = std::min(2, n);
     for (int k = 1; k <= maxk; ++k) {
@@ -756,8 +753,6 @@ void autotune(jq_batch* b, const jq_exec_opts* opts) {
         g_tuned_kb[{b->enc, n}] = best[n];
         for (size_t i : by_n[n]) b->kb[i] = best[n];
     }
-    (void)saved;
-    (void)cost;
 }
 
 }  // namespace
