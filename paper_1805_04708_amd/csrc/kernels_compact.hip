@@ -766,7 +766,6 @@ __device__ __forceinline__ void hc_perm_reg_dispatch(uint32_t (&c)[P], int j, ui
         case 4: hc_perm_reg<P, 4>(c, rc, thr_ok); asm volatile("; code slot 4"); break;
         case 5: hc_perm_reg<P, 5>(c, rc, thr_ok); asm volatile("; code slot 5"); break;
         case 6: hc_perm_reg<P, 6>(c, rc, thr_ok); asm volatile("; code slot 6"); break;
-        case 7: hc_perm_reg<P, 7>(c, rc, thr_ok); asm volatile("; code slot 7"); break;
         default: break;
     }
 }
@@ -828,7 +827,6 @@ __device__ __forceinline__ void hc_add_mask(uint32_t (&c)[P], uint32_t m, uint32
         case 8u: hc_add_bit<P, 4>(c, y); asm volatile("; add slot 4"); return;
         case 16u: hc_add_bit<P, 5>(c, y); asm volatile("; add slot 5"); return;
         case 32u: hc_add_bit<P, 6>(c, y); asm volatile("; add slot 6"); return;
-        case 64u: hc_add_bit<P, 7>(c, y); asm volatile("; add slot 7"); return;
         default: break;
     }
 #pragma unroll
