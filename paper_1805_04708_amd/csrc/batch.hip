@@ -692,6 +692,15 @@ float timed_launch(jq_batch* b) {
     return ms;
 }
 
+// A tuning trial: the best of three launches after a warm-up launch (one
+// launch alone is too noisy to compare modes that differ by 10%).
+float trial_ms(jq_batch* b) {
+    timed_launch(b);
+    float best = timed_launch(b);
+    for (int r = 0; r < 2; ++r) best = std::min(best, timed_launch(b));
+    return best;
+}
+
 // Fusion depth per (encoding, N): the first batch that meets an untuned N
 // times every depth on its circuits of that N (all depths give the same
 // state up to rounding) and keeps the fastest for the rest of the process,
@@ -724,8 +733,7 @@ void autotune(jq_batch* b, const jq_exec_opts* opts) {
         for (int n : untuned)
             for (size_t i : by_n[n]) b->kb[i] = std::min(k, n);
         upload_plans(b);
-        timed_launch(b);  // warm
-        const float ms = timed_launch(b);
+        const float ms = trial_ms(b);
         if (k == 1 || ms < best_ms) {
             best_ms = ms;
             for (int n : untuned) best[n] = std::min(k, n);
@@ -740,8 +748,7 @@ void autotune(jq_batch* b, const jq_exec_opts* opts) {
         if (!tile_capable(b, n)) continue;
         for (size_t i : by_n[n]) b->kb[i] = kTileDepth;
         upload_plans(b);
-        timed_launch(b);  // warm
-        const float ms = timed_launch(b);
+        const float ms = trial_ms(b);
         if (ms < best_ms) {
             best_ms = ms;
             best[n] = kTileDepth;
