@@ -163,6 +163,11 @@ struct PlanConfig {
     // every run of fusable gates becomes a pass, however few bytes single
     // gates would move (states that stay in the caches)
     bool always_pass = false;
+    // rounds of the tile-slot search (0: first come, first served)
+    int search_rounds = 2;
+    // time of a pass's streaming in units of one op's arithmetic (weighs
+    // fewer passes against more ops in the search)
+    double pass_ops = 18.0;
 };
 
 struct Plan {

@@ -14,6 +14,13 @@
 // Gates may be taken out of order only past gates they commute with: a
 // gate joins the pass only if it shares no qubit with any gate skipped so
 // far (diagonal gates may pass skipped diagonal gates).
+//
+// Which qubits take the free tile slots decides how far a pass gets: a scan
+// that fills them first come, first served can spend a slot on a qubit that
+// stalls at once (a CNOT from a qubit that is still behind, say).  Each pass
+// therefore also tries scans that shut one of the chosen qubits out and keeps
+// the one that retires the most work per unit of estimated pass time (a
+// fixed streaming cost plus the arithmetic of its ops).
 #include <algorithm>
 
 #include "internal.hpp"
@@ -26,6 +33,7 @@ namespace {
 // fixed lane bits); the builder places the other targets.
 struct PassBuilder {
     int n, F, K, max_ops, R;
+    uint64_t banned;          // qubits this pass may not place
     std::vector<int> reg_q;   // qubits in the free register slots R..K-1
     std::vector<int> lane_q;  // qubits in lane bits F..5
     std::vector<int> taken;   // op indices
@@ -35,14 +43,26 @@ struct PassBuilder {
         for (int q : lane_q) t |= 1ull << q;
         return t;
     }
-    // can target q be placed (or is it already)?  Places it if so.
-    bool place(int q) {
-        if (q < R + F) return true;
-        if (std::find(reg_q.begin(), reg_q.end(), q) != reg_q.end()) return true;
-        if (std::find(lane_q.begin(), lane_q.end(), q) != lane_q.end()) return true;
-        if ((int)reg_q.size() < K - R) { reg_q.push_back(q); return true; }
-        if ((int)lane_q.size() < 6 - F) { lane_q.push_back(q); return true; }
-        return false;
+    bool holds(int q) const {
+        return q < R + F || std::find(reg_q.begin(), reg_q.end(), q) != reg_q.end() ||
+               std::find(lane_q.begin(), lane_q.end(), q) != lane_q.end();
+    }
+    // Can targets q0 and q1 (-1: none) be placed (or are they already)?
+    // Places them if so (register slots first), else changes nothing.
+    bool place(int q0, int q1 = -1) {
+        int add[2], n_add = 0;
+        for (int q : {q0, q1}) {
+            if (q < 0 || holds(q) || (n_add == 1 && add[0] == q)) continue;
+            if ((banned >> q) & 1) return false;
+            add[n_add++] = q;
+        }
+        const int free_slots = (K - R - (int)reg_q.size()) + (6 - F - (int)lane_q.size());
+        if (n_add > free_slots) return false;
+        for (int i = 0; i < n_add; ++i) {
+            if ((int)reg_q.size() < K - R) reg_q.push_back(add[i]);
+            else lane_q.push_back(add[i]);
+        }
+        return true;
     }
 };
 
@@ -392,8 +412,12 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
     std::vector<int> remaining(ops.size());
     for (size_t i = 0; i < ops.size(); i++) remaining[i] = (int)i;
     const size_t window = 4096;
-    while (!remaining.empty()) {
-        PassBuilder pb{n, F, K, cfg.max_ops, cfg.fixed_reg_bits, {}, {}, {}};
+    std::vector<char> fus(ops.size());
+    for (size_t i = 0; i < ops.size(); ++i) fus[i] = fusable(ops[i], cfg);
+    // One scan: take every gate, in order, that can join the pass; targets
+    // take the free tile slots first come, first served.
+    auto scan = [&](uint64_t banned) {
+        PassBuilder pb{n, F, K, cfg.max_ops, cfg.fixed_reg_bits, banned, {}, {}, {}};
         uint64_t blk_any = 0, blk_diag = 0;
         size_t scanned = 0;
         for (size_t r = 0; r < remaining.size() && scanned < window; r++, scanned++) {
@@ -402,18 +426,16 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
             const bool diag = op.kind == OP_DIAG;
             // on the two-byte code with per-gate quantisation no gate may move
             // past one that decodes: the scan ends there
-            if (cfg.code_domain && !fusable(op, cfg)) break;
+            if (cfg.code_domain && !fus[remaining[r]]) break;
             if ((sup & blk_any) || (!diag && (sup & blk_diag))) {
                 (diag ? blk_diag : blk_any) |= sup;
                 continue;
             }
             bool ok = true;
-            if (!fusable(op, cfg)) {
+            if (!fus[remaining[r]]) {
                 ok = false;  // two-qubit dense blocks run unfused
             } else if (!diag) {
-                PassBuilder trial = pb;
-                ok = trial.place(op.t0) && (op.kind != OP_DENSE2 || trial.place(op.t1));
-                if (ok) pb = trial;
+                ok = pb.place(op.t0, op.kind == OP_DENSE2 ? op.t1 : -1);
             }
             if (!ok) {
                 (diag ? blk_diag : blk_any) |= sup;
@@ -421,6 +443,93 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
             }
             pb.taken.push_back(remaining[r]);
             if ((int)pb.taken.size() >= cfg.max_ops) break;
+        }
+        return pb;
+    };
+    // Work a pass retires: non-diagonal gates count four times as much as
+    // diagonal ones, which need no tile slot.
+    auto work = [&](const PassBuilder& b) {
+        int w = 0;
+        for (int i : b.taken) w += ops[i].kind == OP_DIAG ? 1 : 4;
+        return w;
+    };
+    const int R = cfg.fixed_reg_bits;
+    // The pass layout for a builder (unused slots take the lowest qubits
+    // outside the tile) and its op list after folding diagonals and merging
+    // same-target gates; n_ops counts the kernel ops (a SWAP is three).
+    struct Layout {
+        FPass p;
+        std::vector<PassOp> pops;
+        int n_ops;
+    };
+    auto layout = [&](PassBuilder pb) {
+        Layout L;
+        uint64_t t = pb.tile();
+        auto next_free = [&]() {
+            for (int q = 0; q < n; q++)
+                if (!(t & (1ull << q))) { t |= 1ull << q; return q; }
+            fail(JQ_EDEVICE, "planner: no free qubit");
+        };
+        while ((int)pb.lane_q.size() < 6 - F) pb.lane_q.push_back(next_free());
+        while ((int)pb.reg_q.size() < K - R) pb.reg_q.push_back(next_free());
+        FPass& p = L.p;
+        std::memset(&p, 0, sizeof(p));
+        for (int j = 0; j < 8; j++) p.reg_q[j] = j < R ? j : j < K ? pb.reg_q[j - R] : -1;
+        for (int b = 0; b < 6; b++) p.lane_q[b] = b < F ? R + b : pb.lane_q[b - F];
+        std::vector<int> tb;
+        for (int b = 0; b < 6; b++) tb.push_back(p.lane_q[b]);
+        for (int j = 0; j < K; j++) tb.push_back(p.reg_q[j]);
+        std::sort(tb.begin(), tb.end());
+        p.n_tile = (int)tb.size();
+        for (int i = 0; i < p.n_tile; i++) p.tile_sorted[i] = tb[i];
+        L.pops.resize(pb.taken.size());
+        for (size_t i = 0; i < pb.taken.size(); ++i) {
+            L.pops[i].op = ops[pb.taken[i]];
+            for (int e = 0; e < 4; ++e) L.pops[i].mats[0][e] = L.pops[i].op.m[e];
+        }
+        uint64_t reg_bits = 0;
+        for (int j = 0; j < K; ++j) reg_bits |= 1ull << p.reg_q[j];
+        if (cfg.absorb) {
+            absorb_diagonals(L.pops, reg_bits);
+            merge_same_target(L.pops);
+        }
+        L.n_ops = 0;
+        for (const auto& po : L.pops)
+            if (po.alive) L.n_ops += is_swap(po.op) ? 3 : 1;
+        return L;
+    };
+    // Work per unit of pass time, the time being pass_ops (the pass's
+    // streaming, in units of one op's arithmetic) plus its ops.
+    auto rate = [&](const PassBuilder& b, const Layout& L) {
+        return (double)work(b) / (cfg.pass_ops + L.n_ops);
+    };
+    while (!remaining.empty()) {
+        // First come, first served can fill the tile with qubits that block
+        // early (a gate coupling them to a qubit outside the tile that is
+        // still behind); shutting one placed qubit out of the pass lets a
+        // later one in.  Keep the scan with the best rate, a few times over.
+        PassBuilder pb = scan(0);
+        Layout L;
+        if (!pb.taken.empty()) L = layout(pb);
+        for (int it = 0; it < cfg.search_rounds && !pb.taken.empty(); ++it) {
+            std::vector<int> placed = pb.reg_q;
+            placed.insert(placed.end(), pb.lane_q.begin(), pb.lane_q.end());
+            const uint64_t banned = pb.banned;
+            double best = rate(pb, L);
+            bool moved = false;
+            for (int q : placed) {
+                PassBuilder c = scan(banned | (1ull << q));
+                if (c.taken.empty()) continue;
+                Layout Lc = layout(c);
+                const double rc = rate(c, Lc);
+                if (rc > best) {
+                    best = rc;
+                    pb = std::move(c);
+                    L = std::move(Lc);
+                    moved = true;
+                }
+            }
+            if (!moved) break;
         }
         if (pb.taken.empty()) {
             // the first remaining gate cannot run fused: run it alone
@@ -451,43 +560,14 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
             }
             continue;
         }
-        // fill unused slots with the lowest qubits outside the tile
-        uint64_t t = pb.tile();
-        auto next_free = [&]() {
-            for (int q = 0; q < n; q++)
-                if (!(t & (1ull << q))) { t |= 1ull << q; return q; }
-            fail(JQ_EDEVICE, "planner: no free qubit");
-        };
-        const int R = cfg.fixed_reg_bits;
-        while ((int)pb.lane_q.size() < 6 - F) pb.lane_q.push_back(next_free());
-        while ((int)pb.reg_q.size() < K - R) pb.reg_q.push_back(next_free());
         Step s;
         s.fused = true;
         s.k_reg = K;
-        FPass& p = s.pass;
-        std::memset(&p, 0, sizeof(p));
-        for (int j = 0; j < 8; j++) p.reg_q[j] = j < R ? j : j < K ? pb.reg_q[j - R] : -1;
-        for (int b = 0; b < 6; b++) p.lane_q[b] = b < F ? R + b : pb.lane_q[b - F];
-        std::vector<int> tb;
-        for (int b = 0; b < 6; b++) tb.push_back(p.lane_q[b]);
-        for (int j = 0; j < K; j++) tb.push_back(p.reg_q[j]);
-        std::sort(tb.begin(), tb.end());
-        p.n_tile = (int)tb.size();
-        for (int i = 0; i < p.n_tile; i++) p.tile_sorted[i] = tb[i];
+        s.pass = L.p;
+        const FPass& p = s.pass;
         s.first_fop = plan.fops.size();
-        std::vector<PassOp> pops(pb.taken.size());
-        for (size_t i = 0; i < pb.taken.size(); ++i) {
-            pops[i].op = ops[pb.taken[i]];
-            for (int e = 0; e < 4; ++e) pops[i].mats[0][e] = pops[i].op.m[e];
-        }
-        uint64_t reg_bits = 0;
-        for (int j = 0; j < K; ++j) reg_bits |= 1ull << p.reg_q[j];
-        if (cfg.absorb) {
-            absorb_diagonals(pops, reg_bits);
-            merge_same_target(pops);
-        }
         int n_ops = 0;
-        for (auto& po : pops) {
+        for (auto& po : L.pops) {
             if (!po.alive) continue;
             if (is_swap(po.op)) {
                 // SWAP(a, b) = X on b where a = 1, X on a where b = 1, X on b
@@ -512,7 +592,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
             plan.fops.push_back(lower_fop(po.op, p, F, K, po.nsel, po.sel, po.mats, cfg.code_domain));
             ++n_ops;
         }
-        p.n_ops = n_ops;
+        s.pass.n_ops = n_ops;
         s.n_gates = pb.taken.size();
         s.gates = pb.taken;
         plan.steps.push_back(s);

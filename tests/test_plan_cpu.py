@@ -220,3 +220,37 @@ def test_compact_rz_cnot_layer_is_a_few_passes():
     # one register qubit fewer per pass: more passes
     _, blen6, _ = schedule(n, "compact", circ, fusion=6)
     assert len(blen6) > len(blen)
+
+
+@pytest.mark.parametrize("enc,kw", [("c128", {}), ("c64", {}), ("compact", {})])
+def test_deep_circuits_reorder_only_commuting_gates(enc, kw):
+    # many layers give the tile-slot search room to pull later gates of some
+    # qubits ahead of earlier gates of others; the result must stay the same
+    # unitary
+    n = 13
+    circs = [W.rz_cnot_chain(n, 25, seed=6)]
+    if enc != "compact":  # Haar U(2) gates never run in code passes
+        circs.append(W.layered_u2_cz(n, 25, seed=5))
+    for circ in circs:
+        order, blen, fused = schedule(n, enc, circ, **kw)
+        assert sorted(order) == non_identity(circ)
+        rng = np.random.default_rng(3)
+        psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+        psi /= np.linalg.norm(psi)
+        a = O.run(psi.copy(), n, circ)
+        b = O.run(psi.copy(), n, [circ[i] for i in order])
+        assert O.rel_l2(b, a) < 1e-12
+
+
+def test_tile_slot_search_shortens_rz_cnot_chains():
+    # 40 layers of RZ + CNOT chain at N=30 (complex128: 7 free tile qubits per
+    # pass).  Filling the slots first come, first served stalls on CNOTs
+    # whose control is still behind (144 passes); letting a later qubit take
+    # the slot of one that stalls early retires the circuit in 61
+    n = 30
+    circ = W.rz_cnot_chain(n, 40, seed=7)
+    order, blen, fused = schedule(n, "c128", circ)
+    assert all(fused) and len(blen) <= 66, len(blen)
+    # the layered Haar U(2) + CZ circuit: 62 passes before the search
+    _, blen, fused = schedule(n, "c128", W.layered_u2_cz(n, 40, seed=2018))
+    assert all(fused) and len(blen) <= 57, len(blen)
