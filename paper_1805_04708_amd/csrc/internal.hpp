@@ -164,7 +164,7 @@ struct PlanConfig {
     // gates would move (states that stay in the caches)
     bool always_pass = false;
     // rounds of the tile-slot search (0: first come, first served)
-    int search_rounds = 2;
+    int search_rounds = 0;
     // time of a pass's streaming in units of one op's arithmetic (weighs
     // fewer passes against more ops in the search)
     double pass_ops = 18.0;
