@@ -531,6 +531,35 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
             }
             if (!moved) break;
         }
+        // Which placed qubits sit in register slots and which in lane bits
+        // decides what folds: a multiplexer selector must not be a register
+        // slot, so a CZ to a register qubit stays an op of its own and keeps
+        // the gates on either side of it from merging.  When a diagonal is
+        // left over next to a foldable gate, try other splits and keep the
+        // one with fewer ops, one swap at a time.
+        if (cfg.search_rounds > 0 && cfg.absorb && !pb.taken.empty()) {
+            bool dense = false, diag_left = false;
+            for (const auto& po : L.pops) {
+                if (!po.alive) continue;
+                dense = dense || absorbable(po);
+                diag_left = diag_left || po.op.kind == OP_DIAG;
+            }
+            // swap a register qubit with a lane qubit while that saves ops
+            for (bool better = dense && diag_left; better;) {
+                better = false;
+                for (size_t i = 0; i < pb.reg_q.size() && !better; ++i)
+                    for (size_t j = 0; j < pb.lane_q.size() && !better; ++j) {
+                        PassBuilder c = pb;
+                        std::swap(c.reg_q[i], c.lane_q[j]);
+                        Layout Lc = layout(c);
+                        if (Lc.n_ops < L.n_ops) {
+                            pb = std::move(c);
+                            L = std::move(Lc);
+                            better = true;
+                        }
+                    }
+            }
+        }
         if (pb.taken.empty()) {
             // the first remaining gate cannot run fused: run it alone
             Step s;
