@@ -560,6 +560,23 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
                     }
             }
         }
+        // Lane bit 5 exchanges through the LDS crossbar (a permute), the
+        // lower lane bits by swizzles: give the highest lane bits to the
+        // qubits that carry the fewest ops.
+        if (cfg.search_rounds > 0 && pb.lane_q.size() > 1) {
+            auto lane_ops = [&](int q) {
+                int c = 0;
+                for (const auto& po : L.pops)
+                    if (po.alive && po.op.kind != OP_DIAG && po.op.t0 == q) ++c;
+                return c;
+            };
+            std::vector<int> lq = pb.lane_q;
+            std::stable_sort(lq.begin(), lq.end(), [&](int a, int b) { return lane_ops(a) > lane_ops(b); });
+            if (lq != pb.lane_q) {
+                pb.lane_q = lq;
+                L = layout(pb);
+            }
+        }
         if (pb.taken.empty()) {
             // the first remaining gate cannot run fused: run it alone
             Step s;
