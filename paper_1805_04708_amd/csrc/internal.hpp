@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <deque>
+#include <functional>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -175,7 +177,11 @@ struct Plan {
     std::vector<FOp> fops;
 };
 
-Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg);
+// Called after each step is appended (plan.steps.back(); a fused step's
+// ops are at the end of plan.fops), so a caller can launch steps while the
+// rest is still being planned.
+using StepSink = std::function<void(Plan&)>;
+Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const StepSink& on_step = {});
 
 // ------------------------------------------------------------ kernels --
 
@@ -302,9 +308,17 @@ struct jq_state {
         double ms = 0, bytes = 0;
     };
     std::vector<Acc> acc;
-    // fused-op list: device copy, pinned staging, event of the last upload
+    // fused-op list: with stream-ordered allocation, a device copy of the
+    // last plan; without, a ring of plan_dev_bytes in device memory and in
+    // pinned staging, filled from ring_head on, with the copies still to run
     void* plan_dev = nullptr;
     void* plan_host = nullptr;
     size_t plan_dev_bytes = 0;
-    hipEvent_t plan_ev = nullptr;
+    struct RingUse {
+        size_t off, n;  // FOp slots
+        hipEvent_t ev;  // recorded after the copy out of them
+    };
+    size_t ring_head = 0;
+    std::deque<RingUse> ring_busy;
+    std::vector<hipEvent_t> ring_ev_free;
 };

@@ -395,8 +395,12 @@ void merge_same_target(std::vector<PassOp>& ops) {
 
 }  // namespace
 
-Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
+Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const StepSink& on_step) {
     Plan plan;
+    auto emit = [&](Step&& s) {
+        plan.steps.push_back(std::move(s));
+        if (on_step) on_step(plan);
+    };
     const int n = cfg.n, F = cfg.fixed_lane_bits, K = cfg.k_reg;
     const bool can_fuse = cfg.fuse && K >= 1 && K >= cfg.fixed_reg_bits && n >= 6 + K && 6 + K <= kMaxTileBits;
     if (!can_fuse) {
@@ -405,7 +409,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
             s.op = op;
             s.n_gates = 1;
             s.gates.push_back((int)plan.steps.size());
-            plan.steps.push_back(s);
+            emit(std::move(s));
         }
         return plan;
     }
@@ -583,7 +587,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
             s.op = ops[remaining[0]];
             s.n_gates = 1;
             s.gates.push_back(remaining[0]);
-            plan.steps.push_back(s);
+            emit(std::move(s));
             remaining.erase(remaining.begin());
             continue;
         }
@@ -602,7 +606,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
                 s.op = ops[i];
                 s.n_gates = 1;
                 s.gates.push_back(i);
-                plan.steps.push_back(s);
+                emit(std::move(s));
             }
             continue;
         }
@@ -641,7 +645,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg) {
         s.pass.n_ops = n_ops;
         s.n_gates = pb.taken.size();
         s.gates = pb.taken;
-        plan.steps.push_back(s);
+        emit(std::move(s));
     }
     return plan;
 }

@@ -212,68 +212,129 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
     return c;
 }
 
-// Copy the fused-op list to the device: pinned staging buffer (reused once
-// the previous copy out of it has finished) -> device buffer (reused in
-// stream order, after every kernel that read the previous plan).
+// Copy the fused-op list of a state with stream-ordered allocation to the
+// device (its buffer is reused in stream order, after every kernel that read
+// the previous plan).
 void upload_fops(jq_state* s, const std::vector<FOp>& fops) {
     const size_t bytes = fops.size() * sizeof(FOp);
     if (bytes == 0) return;
-    if (s->async_alloc) {
-        if (bytes > s->plan_dev_bytes) {
-            if (s->plan_dev) JQ_HIP(hipFreeAsync(s->plan_dev, s->stream));
-            s->plan_dev = nullptr;
-            JQ_HIP(hipMallocAsync(&s->plan_dev, bytes, s->stream));
-            s->plan_dev_bytes = bytes;
-        }
-        // pageable source: the runtime stages it before the call returns
-        JQ_HIP(hipMemcpyAsync(s->plan_dev, fops.data(), bytes, hipMemcpyHostToDevice, s->stream));
-        return;
-    }
-    if (s->plan_ev) JQ_HIP(hipEventSynchronize(s->plan_ev));
     if (bytes > s->plan_dev_bytes) {
+        if (s->plan_dev) JQ_HIP(hipFreeAsync(s->plan_dev, s->stream));
+        s->plan_dev = nullptr;
+        JQ_HIP(hipMallocAsync(&s->plan_dev, bytes, s->stream));
+        s->plan_dev_bytes = bytes;
+    }
+    // pageable source: the runtime stages it before the call returns
+    JQ_HIP(hipMemcpyAsync(s->plan_dev, fops.data(), bytes, hipMemcpyHostToDevice, s->stream));
+}
+
+// Copy n fused ops into the ring and return their device address.  A copy
+// runs in stream order, after every kernel that read the slots before, so
+// only the pinned staging needs a wait: slots whose earlier copy has not yet
+// run are not written until it has.
+const FOp* ring_put(jq_state* s, const FOp* src, size_t n) {
+    const size_t cap = s->plan_dev_bytes / sizeof(FOp);
+    if (n > cap) {
         JQ_HIP(hipStreamSynchronize(s->stream));
+        for (auto& u : s->ring_busy) s->ring_ev_free.push_back(u.ev);
+        s->ring_busy.clear();
         if (s->plan_dev) JQ_HIP(hipFree(s->plan_dev));
         if (s->plan_host) JQ_HIP(hipHostFree(s->plan_host));
         s->plan_dev = nullptr;
         s->plan_host = nullptr;
-        const size_t cap = std::max<size_t>(bytes * 2, 64 * 1024);
-        JQ_HIP(hipMalloc(&s->plan_dev, cap));
-        JQ_HIP(hipHostMalloc(&s->plan_host, cap, hipHostMallocDefault));
-        s->plan_dev_bytes = cap;
+        s->plan_dev_bytes = 0;
+        const size_t bytes = std::max<size_t>(1024, 4 * n) * sizeof(FOp);
+        JQ_HIP(hipMalloc(&s->plan_dev, bytes));
+        JQ_HIP(hipHostMalloc(&s->plan_host, bytes, hipHostMallocDefault));
+        s->plan_dev_bytes = bytes;
+        s->ring_head = 0;
+        return ring_put(s, src, n);
     }
-    if (!s->plan_ev) JQ_HIP(hipEventCreateWithFlags(&s->plan_ev, hipEventDisableTiming));
-    std::memcpy(s->plan_host, fops.data(), bytes);
-    JQ_HIP(hipMemcpyAsync(s->plan_dev, s->plan_host, bytes, hipMemcpyHostToDevice, s->stream));
-    JQ_HIP(hipEventRecord(s->plan_ev, s->stream));
+    size_t off = s->ring_head;
+    if (off + n > cap) off = 0;
+    // the newest pending copy out of [off, off + n); the older ones have
+    // run once it has
+    size_t last = 0;
+    for (size_t i = 0; i < s->ring_busy.size(); ++i) {
+        const auto& u = s->ring_busy[i];
+        if (u.off < off + n && off < u.off + u.n) last = i + 1;
+    }
+    if (last) JQ_HIP(hipEventSynchronize(s->ring_busy[last - 1].ev));
+    for (size_t i = 0; i < last; ++i) {
+        s->ring_ev_free.push_back(s->ring_busy.front().ev);
+        s->ring_busy.pop_front();
+    }
+    FOp* host = static_cast<FOp*>(s->plan_host) + off;
+    FOp* dev = static_cast<FOp*>(s->plan_dev) + off;
+    std::memcpy(host, src, n * sizeof(FOp));
+    JQ_HIP(hipMemcpyAsync(dev, host, n * sizeof(FOp), hipMemcpyHostToDevice, s->stream));
+    hipEvent_t ev;
+    if (s->ring_ev_free.empty()) {
+        JQ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    } else {
+        ev = s->ring_ev_free.back();
+        s->ring_ev_free.pop_back();
+    }
+    JQ_HIP(hipEventRecord(ev, s->stream));
+    s->ring_busy.push_back({off, n, ev});
+    s->ring_head = off + n;
+    return dev;
+}
+
+void run_step(jq_state* s, const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step& step,
+              const FOp* dev_ops) {
+    if (!step.fused) {
+        run_single(s, step.op);
+        return;
+    }
+    const double sweep = std::ldexp(1.0, s->n) * bytes_per_amp(s->enc);
+    FPass p = step.pass;
+    p.ops = dev_ops;
+    if (s->enc == JQ_COMPACT && cfg.code_domain) {
+        Timed t(s, K_CP_CODES, 2.0 * sweep);
+        cp_apply_codes(compact_bufs(s), s->n, p, step.k_reg, cfg.fixed_reg_bits, s->stream);
+        return;
+    }
+    if (s->enc == JQ_COMPACT) {
+        bool keeps = true;
+        for (int g : step.gates) keeps = keeps && ops[g].keeps_modulus;
+        Timed t(s, K_CP_FUSED, (keeps ? 2.0 : 3.0) * sweep);
+        cp_apply_block(compact_bufs(s), s->n, p, step.k_reg, cfg.fixed_lane_bits, keeps, s->stream);
+        return;
+    }
+    Timed t(s, K_FUSED, 2.0 * sweep);
+    sv_apply_fused(s->enc, s->buf, s->n, p, step.k_reg, cfg.fixed_lane_bits, s->stream);
 }
 
 void apply_ops(jq_state* s, const std::vector<GateOp>& ops, const PlanConfig& cfg) {
-    Plan plan = make_plan(ops, cfg);
-    upload_fops(s, plan.fops);
-    const FOp* dev = (const FOp*)s->plan_dev;
-    const double sweep = std::ldexp(1.0, s->n) * bytes_per_amp(s->enc);
-    for (auto& step : plan.steps) {
-        if (!step.fused) {
-            run_single(s, step.op);
-            continue;
-        }
-        FPass p = step.pass;
-        p.ops = dev + step.first_fop;
-        if (s->enc == JQ_COMPACT && cfg.code_domain) {
-            Timed t(s, K_CP_CODES, 2.0 * sweep);
-            cp_apply_codes(compact_bufs(s), s->n, p, step.k_reg, cfg.fixed_reg_bits, s->stream);
-            continue;
-        }
-        if (s->enc == JQ_COMPACT) {
-            bool keeps = true;
-            for (int g : step.gates) keeps = keeps && ops[g].keeps_modulus;
-            Timed t(s, K_CP_FUSED, (keeps ? 2.0 : 3.0) * sweep);
-            cp_apply_block(compact_bufs(s), s->n, p, step.k_reg, cfg.fixed_lane_bits, keeps, s->stream);
-            continue;
-        }
-        Timed t(s, K_FUSED, 2.0 * sweep);
-        sv_apply_fused(s->enc, s->buf, s->n, p, step.k_reg, cfg.fixed_lane_bits, s->stream);
+    if (s->async_alloc) {
+        // served states: plan, upload, launch
+        Plan plan = make_plan(ops, cfg);
+        upload_fops(s, plan.fops);
+        const FOp* dev = (const FOp*)s->plan_dev;
+        for (const auto& step : plan.steps) run_step(s, ops, cfg, step, dev + step.first_fop);
+        return;
     }
+    // Launch steps while the rest is planned: the first fused pass as soon
+    // as it is planned, then every few passes, so the device is busy while
+    // the host plans.
+    size_t launched = 0, uploaded = 0, flushes = 0;
+    auto flush = [&](Plan& plan) {
+        const size_t n = plan.fops.size() - uploaded;
+        const FOp* dev = n ? ring_put(s, plan.fops.data() + uploaded, n) : nullptr;
+        for (; launched < plan.steps.size(); ++launched) {
+            const Step& st = plan.steps[launched];
+            run_step(s, ops, cfg, st, st.fused ? dev + (st.first_fop - uploaded) : nullptr);
+        }
+        uploaded = plan.fops.size();
+        ++flushes;
+    };
+    Plan plan = make_plan(ops, cfg, [&](Plan& pl) {
+        size_t waiting = 0;
+        for (size_t i = launched; i < pl.steps.size(); ++i) waiting += pl.steps[i].fused;
+        if (waiting >= (flushes ? 4u : 1u) || !pl.steps.back().fused) flush(pl);
+    });
+    if (launched < plan.steps.size()) flush(plan);
 }
 
 void do_probabilities(jq_state* s, const int* qubits, int nq, double* out_host) {
@@ -434,7 +495,6 @@ int jq_state_destroy(jq_state* s) {
             if (s->buf) (void)hipFreeAsync(s->buf, s->stream);
             if (s->aux) (void)hipFreeAsync(s->aux, s->stream);
             if (s->plan_dev) (void)hipFreeAsync(s->plan_dev, s->stream);
-            if (s->plan_ev) (void)hipEventDestroy(s->plan_ev);
             delete s;
             return;
         }
@@ -451,7 +511,8 @@ int jq_state_destroy(jq_state* s) {
         if (s->aux) (void)hipFree(s->aux);
         if (s->plan_dev) (void)hipFree(s->plan_dev);
         if (s->plan_host) (void)hipHostFree(s->plan_host);
-        if (s->plan_ev) (void)hipEventDestroy(s->plan_ev);
+        for (auto& u : s->ring_busy) (void)hipEventDestroy(u.ev);
+        for (auto ev : s->ring_ev_free) (void)hipEventDestroy(ev);
         if (s->own_stream) (void)hipStreamDestroy(s->stream);
         delete s;
         hip_check(e, "jq_state_destroy: pending work failed");
