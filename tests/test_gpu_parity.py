@@ -467,3 +467,33 @@ def test_compact_rz_cnot_chain_matches_oracle_codes():
     assert np.array_equal(b0, st.b0)
     d1 = np.abs(((b1.astype(int) - st.b1.astype(int)) + 128) % 256 - 128)
     assert np.mean(d1 == 0) >= 1 - 1e-4 and d1.max() <= 1
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+def test_fused_op_ring_wraps_and_grows(enc):
+    # one state, many calls: the fused ops of each call go to the device
+    # through a ring (about a thousand ops) that wraps around across calls
+    # and grows when one upload needs more (passes of up to 256 SWAPs, three
+    # ops each); every call must still match the oracle
+    n = 14
+    rng = np.random.default_rng(21)
+    psi = rand_state(rng, n)
+    ref = psi.copy()
+    total = 0
+    with jq.State(n, enc) as s:
+        s.write_amplitudes(psi)
+        for k in range(10):
+            circ = W.layered_u2_cz(n, 20, seed=100 + k)
+            s.apply_circuit(circ)
+            ref = O.run(ref, n, circ)
+            total += len(circ)
+            got = s.amplitudes()
+            assert O.rel_l2(got, ref) <= tol(enc, total), (k, O.rel_l2(got, ref))
+        swaps = []
+        for _ in range(1500):  # qubits 0..9 fit one tile: 256 SWAPs a pass
+            a, b = rng.choice(10, size=2, replace=False)
+            swaps.append(("SWAP", (int(a), int(b)), ()))
+        s.apply_circuit(swaps, max_ops=256)
+        ref = O.run(ref, n, swaps)
+        got = s.amplitudes()
+        assert O.rel_l2(got, ref) <= tol(enc, total), O.rel_l2(got, ref)
