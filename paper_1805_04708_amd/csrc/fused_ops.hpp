@@ -329,6 +329,34 @@ __device__ __forceinline__ void diag_op(Cx<R> (&a)[1 << K], const FOp* op, uint6
     }
 }
 
+// A group of uncontrolled one-qubit diagonals on lane bits and on index
+// bits outside the tile: one factor per thread, the product of the lane
+// components (chosen per lane) and of the outer ones (the same in every
+// lane, from the tile base, formed in FP64 once per wave).
+template <typename R, int K>
+__device__ __forceinline__ void dgroup_op(Cx<R> (&a)[1 << K], const FOp* op, int lane, uint64_t ubase) {
+    const int n = op->n_od;
+    Cx<double> w{1.0, 0.0};
+    for (int c = 0; c < n; ++c) {
+        if (op->od_where[c] != 2) continue;
+        const int b = (int)((ubase >> op->od_idx[c]) & 1);
+        w = cmul(w, Cx<double>{op->od_m[4 * c + 2 * b], op->od_m[4 * c + 2 * b + 1]});
+    }
+    Cx<R> t{(R)w.re, (R)w.im};
+    for (int c = 0; c < n; ++c) {
+        if (op->od_where[c] != 1) continue;
+        const bool b = (lane >> op->od_idx[c]) & 1;
+        const Cx<R> d0{(R)op->od_m[4 * c], (R)op->od_m[4 * c + 1]};
+        const Cx<R> d1{(R)op->od_m[4 * c + 2], (R)op->od_m[4 * c + 3]};
+        t = cmul(t, csel(b, d1, d0));
+    }
+#pragma unroll
+    for (int s = 0; s < (1 << K); ++s) {
+        a[s] = cmulf(t, a[s]);
+        JQ_SLOT_FENCE();
+    }
+}
+
 template <typename R, int K, int KIND>
 __device__ __forceinline__ void reg_dispatch(Cx<R> (&a)[1 << K], const FOp* op, bool thr_ok, uint64_t base,
                                              uint64_t ubase) {
@@ -456,6 +484,9 @@ __device__ __forceinline__ void run_ops(Cx<R> (&a)[1 << K], const FOp* __restric
                 break;
             case F_DIAG:
                 diag_op<R, K>(a, op, base, ubase, thr_ok);
+                break;
+            case F_DGROUP:
+                dgroup_op<R, K>(a, op, lane, ubase);
                 break;
             default:
                 break;

@@ -100,7 +100,12 @@ enum FOpKind : int32_t {
     F_MDENSE_LANE = 10, // 2x2 on a lane bit chosen by 1-2 selector bits
     F_CSHIFT = 11,      // two-byte code: add the integer m[v] to the phase code (v = selector value),
                         // run as the masked-add terms cs_*
+    F_DGROUP = 12,      // product of n_od uncontrolled one-qubit diagonals on lane bits and
+                        // index bits outside the tile: one factor per thread
 };
+
+
+constexpr int kMaxOdiag = 8;  // components of one F_DGROUP op
 
 struct FOp {
     int32_t kind;
@@ -123,6 +128,12 @@ struct FOp {
     uint32_t cs_reg[4];
     uint32_t cs_add[4];
     uint64_t cs_thr[4];
+    // F_DGROUP: component c acts on lane bit (od_where[c] = 1) or index bit
+    // (od_where[c] = 2) od_idx[c], with values d0, d1 at od_m[4c .. 4c+3]
+    int32_t n_od;
+    int32_t od_where[kMaxOdiag];
+    int32_t od_idx[kMaxOdiag];
+    double od_m[4 * kMaxOdiag];
 };
 
 constexpr int kMaxTileBits = 16;

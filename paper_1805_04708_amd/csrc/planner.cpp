@@ -299,6 +299,55 @@ bool absorbable(const PassOp& p) {
     return p.alive && p.op.kind == OP_DENSE1 && p.op.cmask == 0;
 }
 
+// The ops of a pass in emission order: a single pass op, or a group of
+// uncontrolled one-qubit diagonals on lane or outer qubits that runs as one
+// F_DGROUP op (one factor per thread).  Such diagonals on a qubit outside
+// the tile commute with every op of the pass (none changes that bit): they
+// all run together at its end.  Those on lane qubits group with the
+// diagonals around them, up to the next non-diagonal op; those on register
+// qubits stay ops of their own (a factor per slot).
+struct PassItem {
+    int pop = -1;
+    std::vector<int> group;
+};
+
+std::vector<PassItem> emit_order(const std::vector<PassOp>& pops, uint64_t tile_bits, uint64_t reg_bits,
+                                 bool code_domain) {
+    std::vector<PassItem> out;
+    std::vector<int> run, outer;
+    auto put_group = [&](const std::vector<int>& g, bool always) {
+        if (g.size() == 1 && !always) {
+            out.push_back(PassItem{g[0], {}});
+            return;
+        }
+        for (size_t i = 0; i < g.size(); i += kMaxOdiag) {
+            PassItem it;
+            it.group.assign(g.begin() + i, g.begin() + std::min(g.size(), i + kMaxOdiag));
+            out.push_back(it);
+        }
+    };
+    for (int i = 0; i < (int)pops.size(); ++i) {
+        const PassOp& po = pops[i];
+        if (!po.alive) continue;
+        const bool one = !code_domain && po.op.kind == OP_DIAG && po.op.cmask == 0 && po.op.nsel == 1 &&
+                         !((reg_bits >> po.op.t0) & 1);
+        if (one && !((tile_bits >> po.op.t0) & 1)) {
+            outer.push_back(i);
+        } else if (one) {
+            run.push_back(i);
+        } else if (po.op.kind == OP_DIAG) {
+            out.push_back(PassItem{i, {}});
+        } else {
+            put_group(run, false);
+            run.clear();
+            out.push_back(PassItem{i, {}});
+        }
+    }
+    put_group(run, false);
+    put_group(outer, true);
+    return out;
+}
+
 // Move each diagonal op of the pass onto a neighbouring uncontrolled dense
 // op that acts on one of its qubits, past ops whose (non-diagonal) target
 // lies outside its support; such ops commute with it.
@@ -324,6 +373,12 @@ void absorb_diagonals(std::vector<PassOp>& ops, uint64_t reg_bits) {
         }
         if (done) ops[i].alive = false;
     }
+}
+
+uint64_t lane_bits_of(const FPass& p) {
+    uint64_t m = 0;
+    for (int b = 0; b < 6; ++b) m |= 1ull << p.lane_q[b];
+    return m;
 }
 
 uint64_t sel_mask(const PassOp& p) {
@@ -498,8 +553,8 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step
             merge_same_target(L.pops);
         }
         L.n_ops = 0;
-        for (const auto& po : L.pops)
-            if (po.alive) L.n_ops += is_swap(po.op) ? 3 : 1;
+        for (const auto& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain))
+            L.n_ops += it.pop >= 0 && is_swap(L.pops[it.pop].op) ? 3 : 1;
         return L;
     };
     // Work per unit of pass time, the time being pass_ops (the pass's
@@ -617,8 +672,30 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step
         const FPass& p = s.pass;
         s.first_fop = plan.fops.size();
         int n_ops = 0;
-        for (auto& po : L.pops) {
-            if (!po.alive) continue;
+        uint64_t reg_bits = 0;
+        for (int j = 0; j < K; ++j) reg_bits |= 1ull << p.reg_q[j];
+        for (const PassItem& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain)) {
+            if (it.pop < 0) {
+                FOp f{};
+                f.kind = F_DGROUP;
+                f.sel_reg[0] = f.sel_reg[1] = f.sel_glob[0] = f.sel_glob[1] = -1;
+                f.n_od = (int)it.group.size();
+                for (int c = 0; c < f.n_od; ++c) {
+                    const GateOp& d = L.pops[it.group[c]].op;
+                    f.od_where[c] = 2;
+                    f.od_idx[c] = d.t0;
+                    for (int b = 0; b < 6; ++b)
+                        if (p.lane_q[b] == d.t0) f.od_where[c] = 1, f.od_idx[c] = b;
+                    f.od_m[4 * c] = d.m[0].re;
+                    f.od_m[4 * c + 1] = d.m[0].im;
+                    f.od_m[4 * c + 2] = d.m[1].re;
+                    f.od_m[4 * c + 3] = d.m[1].im;
+                }
+                plan.fops.push_back(f);
+                ++n_ops;
+                continue;
+            }
+            PassOp& po = L.pops[it.pop];
             if (is_swap(po.op)) {
                 // SWAP(a, b) = X on b where a = 1, X on a where b = 1, X on b
                 // where a = 1 (each with the SWAP's own controls as well)

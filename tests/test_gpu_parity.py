@@ -497,3 +497,28 @@ def test_fused_op_ring_wraps_and_grows(enc):
         ref = O.run(ref, n, swaps)
         got = s.amplitudes()
         assert O.rel_l2(got, ref) <= tol(enc, total), O.rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+@pytest.mark.parametrize("n", [12, 16, 21])
+def test_one_qubit_diagonals_run_grouped(enc, n):
+    # layers of one-qubit diagonals (RZ, T, S, Z, U1) on every qubit between
+    # Hadamards and a CNOT chain: in a pass, those on lane qubits and on
+    # qubits outside the tile run as products, one factor per thread
+    rng = np.random.default_rng(n)
+    circ = []
+    for _ in range(6):
+        circ += [("H", (q,), ()) for q in range(0, n, 3)]
+        for q in range(n):
+            k = int(rng.integers(5))
+            if k == 0:
+                circ.append(("RZ", (q,), (float(rng.uniform(0.0, 2.0 * math.pi)),)))
+            elif k == 1:
+                circ.append(("U1", (q,), (float(rng.uniform(0.0, 2.0 * math.pi)),)))
+            else:
+                circ.append((["T", "S", "Z"][k - 2], (q,), ()))
+        circ += [("CNOT", (q, q + 1), ()) for q in range(n - 1)]
+    psi = rand_state(rng, n)
+    got = run_gpu(n, enc, circ, init=psi)
+    ref = run_oracle(n, circ, init=psi)
+    assert O.rel_l2(got, ref) <= tol(enc, len(circ)), O.rel_l2(got, ref)
