@@ -194,7 +194,9 @@ int jq_apply_circuit_noisy(jq_state *s, const jq_gate *gates, size_t count, doub
  * The planner groups gates into blocks (Sec. 5.2 proposes such fusion); a
  * gate may move ahead of earlier gates it commutes with (they share no
  * qubit, or both are diagonal).  order[0..k-1] receives the input index of
- * each non-identity gate in the order applied; block_len[0..*n_blocks-1]
+ * each non-identity gate in the order applied (inside a fused block, gates
+ * that commute with everything between may run at another point of the
+ * block: the product is the same); block_len[0..*n_blocks-1]
  * the number of gates of each consecutive block of that order, and
  * block_fused[b] (may be NULL) 1 for a fused tile pass, 0 for a single-gate
  * kernel.  order, block_len and block_fused need room for count entries.
