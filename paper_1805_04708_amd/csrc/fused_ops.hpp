@@ -329,10 +329,12 @@ __device__ __forceinline__ void diag_op(Cx<R> (&a)[1 << K], const FOp* op, uint6
     }
 }
 
-// A group of uncontrolled one-qubit diagonals on lane bits and on index
-// bits outside the tile: one factor per thread, the product of the lane
-// components (chosen per lane) and of the outer ones (the same in every
-// lane, from the tile base, formed in FP64 once per wave).
+// A group of uncontrolled one-qubit diagonals: one factor per thread, the
+// product of the lane components (chosen per lane) and of the components
+// on index bits outside the tile (the same in every lane, from the tile
+// base, formed in FP64 once per wave); with at most 16 register slots
+// (slot = 1) the register components come as a table of their product per
+// slot.
 template <typename R, int K>
 __device__ __forceinline__ void dgroup_op(Cx<R> (&a)[1 << K], const FOp* op, int lane, uint64_t ubase) {
     const int n = op->n_od;
@@ -349,6 +351,18 @@ __device__ __forceinline__ void dgroup_op(Cx<R> (&a)[1 << K], const FOp* op, int
         const Cx<R> d0{(R)op->od_m[4 * c], (R)op->od_m[4 * c + 1]};
         const Cx<R> d1{(R)op->od_m[4 * c + 2], (R)op->od_m[4 * c + 3]};
         t = cmul(t, csel(b, d1, d0));
+    }
+    if constexpr (K <= 4) {
+        if (op->slot) {
+            // register components: the planner's product per slot
+#pragma unroll
+            for (int s = 0; s < (1 << K); ++s) {
+                const Cx<R> fs = cmul(t, Cx<R>{(R)op->m[2 * s], (R)op->m[2 * s + 1]});
+                a[s] = cmulf(fs, a[s]);
+                JQ_SLOT_FENCE();
+            }
+            return;
+        }
     }
 #pragma unroll
     for (int s = 0; s < (1 << K); ++s) {

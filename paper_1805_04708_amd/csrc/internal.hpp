@@ -100,8 +100,9 @@ enum FOpKind : int32_t {
     F_MDENSE_LANE = 10, // 2x2 on a lane bit chosen by 1-2 selector bits
     F_CSHIFT = 11,      // two-byte code: add the integer m[v] to the phase code (v = selector value),
                         // run as the masked-add terms cs_*
-    F_DGROUP = 12,      // product of n_od uncontrolled one-qubit diagonals on lane bits and
-                        // index bits outside the tile: one factor per thread
+    F_DGROUP = 12,      // product of uncontrolled one-qubit diagonals: n_od on lane bits and
+                        // index bits outside the tile, and (slot = 1, at most 16 slots) those
+                        // on register slots as their product per slot at m[2s], m[2s+1]
 };
 
 

@@ -304,15 +304,16 @@ bool absorbable(const PassOp& p) {
 // F_DGROUP op (one factor per thread).  Such diagonals on a qubit outside
 // the tile commute with every op of the pass (none changes that bit): they
 // all run together at its end.  Those on lane qubits group with the
-// diagonals around them, up to the next non-diagonal op; those on register
-// qubits stay ops of their own (a factor per slot).
+// diagonals around them, up to the next non-diagonal op, and so do those on
+// register qubits when the pass has at most 16 slots (reg_table: their
+// product per slot goes into a table); otherwise they stay ops of their own.
 struct PassItem {
     int pop = -1;
     std::vector<int> group;
 };
 
 std::vector<PassItem> emit_order(const std::vector<PassOp>& pops, uint64_t tile_bits, uint64_t reg_bits,
-                                 bool code_domain) {
+                                 bool code_domain, bool reg_table) {
     std::vector<PassItem> out;
     std::vector<int> run, outer;
     auto put_group = [&](const std::vector<int>& g, bool always) {
@@ -330,7 +331,7 @@ std::vector<PassItem> emit_order(const std::vector<PassOp>& pops, uint64_t tile_
         const PassOp& po = pops[i];
         if (!po.alive) continue;
         const bool one = !code_domain && po.op.kind == OP_DIAG && po.op.cmask == 0 && po.op.nsel == 1 &&
-                         !((reg_bits >> po.op.t0) & 1);
+                         (reg_table || !((reg_bits >> po.op.t0) & 1));
         if (one && !((tile_bits >> po.op.t0) & 1)) {
             outer.push_back(i);
         } else if (one) {
@@ -553,7 +554,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step
             merge_same_target(L.pops);
         }
         L.n_ops = 0;
-        for (const auto& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain))
+        for (const auto& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain, K <= 4))
             L.n_ops += it.pop >= 0 && is_swap(L.pops[it.pop].op) ? 3 : 1;
         return L;
     };
@@ -674,14 +675,32 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step
         int n_ops = 0;
         uint64_t reg_bits = 0;
         for (int j = 0; j < K; ++j) reg_bits |= 1ull << p.reg_q[j];
-        for (const PassItem& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain)) {
+        for (const PassItem& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain, K <= 4)) {
             if (it.pop < 0) {
                 FOp f{};
                 f.kind = F_DGROUP;
                 f.sel_reg[0] = f.sel_reg[1] = f.sel_glob[0] = f.sel_glob[1] = -1;
-                f.n_od = (int)it.group.size();
-                for (int c = 0; c < f.n_od; ++c) {
-                    const GateOp& d = L.pops[it.group[c]].op;
+                // register components: their product per slot, m[2s], m[2s+1]
+                cd table[16];
+                for (auto& e : table) e = {1.0, 0.0};
+                for (int g : it.group) {
+                    const GateOp& d = L.pops[g].op;
+                    for (int j = 0; j < K; ++j) {
+                        if (p.reg_q[j] != d.t0) continue;
+                        f.slot = 1;
+                        for (int s = 0; s < (1 << K); ++s) table[s] = cmulh(table[s], d.m[(s >> j) & 1]);
+                    }
+                }
+                if (f.slot)
+                    for (int s = 0; s < (1 << K); ++s) {
+                        f.m[2 * s] = table[s].re;
+                        f.m[2 * s + 1] = table[s].im;
+                    }
+                f.n_od = 0;
+                for (int g : it.group) {
+                    const GateOp& d = L.pops[g].op;
+                    if ((reg_bits >> d.t0) & 1) continue;
+                    const int c = f.n_od++;
                     f.od_where[c] = 2;
                     f.od_idx[c] = d.t0;
                     for (int b = 0; b < 6; ++b)
