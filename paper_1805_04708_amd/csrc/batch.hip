@@ -568,6 +568,7 @@ bool plan_tiles(jq_batch* b, size_t i, std::vector<FPass>& passes, std::vector<F
         cfg.k_reg = b->enc == JQ_C128 ? TileShape<double>::K : TileShape<float>::K;
         cfg.max_ops = 48;
         cfg.always_pass = true;
+        cfg.f32_table = b->enc == JQ_C64;
         Plan plan = make_plan(b->ops_host[i], cfg);
         bool ok = true;
         for (const Step& st : plan.steps) ok = ok && st.fused;

@@ -101,8 +101,9 @@ enum FOpKind : int32_t {
     F_CSHIFT = 11,      // two-byte code: add the integer m[v] to the phase code (v = selector value),
                         // run as the masked-add terms cs_*
     F_DGROUP = 12,      // product of uncontrolled one-qubit diagonals: n_od on lane bits and
-                        // index bits outside the tile, and (slot = 1, at most 16 slots) those
-                        // on register slots as their product per slot at m[2s], m[2s+1]
+                        // index bits outside the tile, and (slot = 1) those on register slots as
+                        // their product per slot s at m[2s], m[2s+1] (double pairs, at most 16
+                        // slots) or, for complex64, as float pairs over m's bytes (at most 32)
 };
 
 
@@ -182,6 +183,9 @@ struct PlanConfig {
     // time of a pass's streaming in units of one op's arithmetic (weighs
     // fewer passes against more ops in the search)
     double pass_ops = 18.0;
+    // complex64 kernels: per-slot diagonal tables are float pairs (up to 32
+    // slots in FOp::m) instead of double pairs (up to 16)
+    bool f32_table = false;
 };
 
 struct Plan {

@@ -305,8 +305,9 @@ bool absorbable(const PassOp& p) {
 // the tile commute with every op of the pass (none changes that bit): they
 // all run together at its end.  Those on lane qubits group with the
 // diagonals around them, up to the next non-diagonal op, and so do those on
-// register qubits when the pass has at most 16 slots (reg_table: their
-// product per slot goes into a table); otherwise they stay ops of their own.
+// register qubits when the op can hold a table of their product per slot
+// (reg_table: 16 slots of double pairs, or 32 of float pairs for complex64);
+// otherwise they stay ops of their own.
 struct PassItem {
     int pop = -1;
     std::vector<int> group;
@@ -554,7 +555,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step
             merge_same_target(L.pops);
         }
         L.n_ops = 0;
-        for (const auto& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain, K <= 4))
+        for (const auto& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain, K <= (cfg.f32_table ? 5 : 4)))
             L.n_ops += it.pop >= 0 && is_swap(L.pops[it.pop].op) ? 3 : 1;
         return L;
     };
@@ -675,13 +676,13 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step
         int n_ops = 0;
         uint64_t reg_bits = 0;
         for (int j = 0; j < K; ++j) reg_bits |= 1ull << p.reg_q[j];
-        for (const PassItem& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain, K <= 4)) {
+        for (const PassItem& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain, K <= (cfg.f32_table ? 5 : 4))) {
             if (it.pop < 0) {
                 FOp f{};
                 f.kind = F_DGROUP;
                 f.sel_reg[0] = f.sel_reg[1] = f.sel_glob[0] = f.sel_glob[1] = -1;
-                // register components: their product per slot, m[2s], m[2s+1]
-                cd table[16];
+                // register components: their product per slot
+                cd table[32];
                 for (auto& e : table) e = {1.0, 0.0};
                 for (int g : it.group) {
                     const GateOp& d = L.pops[g].op;
@@ -691,11 +692,19 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step
                         for (int s = 0; s < (1 << K); ++s) table[s] = cmulh(table[s], d.m[(s >> j) & 1]);
                     }
                 }
-                if (f.slot)
+                if (f.slot && cfg.f32_table) {
+                    float t32[64];
+                    for (int s = 0; s < (1 << K); ++s) {
+                        t32[2 * s] = (float)table[s].re;
+                        t32[2 * s + 1] = (float)table[s].im;
+                    }
+                    std::memcpy(f.m, t32, sizeof(float) * 2 * (1 << K));
+                } else if (f.slot) {
                     for (int s = 0; s < (1 << K); ++s) {
                         f.m[2 * s] = table[s].re;
                         f.m[2 * s + 1] = table[s].im;
                     }
+                }
                 f.n_od = 0;
                 for (int g : it.group) {
                     const GateOp& d = L.pops[g].op;

@@ -188,6 +188,7 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
     // (complex64: half the bytes, as many instructions per op); the
     // two-byte code's decoding passes are taken as complex128's
     c.pass_ops = enc == JQ_C64 ? 6.0 : 19.0;
+    c.f32_table = enc == JQ_C64;
     // the tile-slot search costs about 0.1 ms of host time per pass: worth
     // it once a pass streams 2 GiB or more
     c.search_rounds = std::ldexp((double)bytes_per_amp(enc), n) >= std::ldexp(1.0, 30) ? 2 : 0;
