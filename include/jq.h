@@ -99,12 +99,26 @@ typedef struct {
  *               PER_BLOCK mode a block is one fused pass (or one gate
  *               the planner leaves unfused); JQ_EINVAL for other values.
  *  max_ops:     upper bound on gates per fused pass (0 = default).
+ *  search:      the planner's large-state steps (a search over which qubits
+ *               take a pass's tile slots, the choice of register vs lane
+ *               slot for each of them, and the order of the lane bits):
+ *               JQ_SEARCH_AUTO (0) = on for states of 1 GiB or more, off
+ *               below; JQ_SEARCH_ON = on at any size; JQ_SEARCH_OFF = off
+ *               at any size; JQ_EINVAL for other values.  The result is
+ *               the same either way up to floating-point rounding; the
+ *               switch exists so that small states can run the plans
+ *               large states get.
+ *  reserved:    must be zero.
  * jq_plan_schedule reports the blocks a circuit will run as. */
+#define JQ_SEARCH_AUTO 0
+#define JQ_SEARCH_ON 1
+#define JQ_SEARCH_OFF 2
 typedef struct {
     int32_t fusion;
     int32_t compact_mode;
     int32_t max_ops;
-    int32_t reserved[5];
+    int32_t search;
+    int32_t reserved[4];
 } jq_exec_opts;
 
 typedef struct jq_state jq_state;
@@ -204,6 +218,26 @@ int jq_apply_circuit_noisy(jq_state *s, const jq_gate *gates, size_t count, doub
  * Validation and errors as jq_apply_circuit. */
 int jq_plan_schedule(int n_qubits, int enc, const jq_gate *gates, size_t count, const jq_exec_opts *opts,
                      int32_t *order, int32_t *block_len, int32_t *block_fused, size_t *n_blocks);
+
+/* One step of the plan of jq_plan_schedule, as the kernels see it. */
+typedef struct {
+    int32_t fused;     /* 1: a fused tile pass (Sec. 5.2's combined gates), 0: one gate alone */
+    int32_t k_reg;     /* register bits of the pass: a lane holds 2^k_reg amplitudes */
+    int32_t reg_q[8];  /* qubit held by register slot j (j < k_reg), else -1 */
+    int32_t lane_q[6]; /* qubit held by lane bit b */
+    int32_t n_gates;   /* source gates of the step */
+    int32_t n_ops;     /* kernel ops of the pass after folding and merging */
+    int32_t table_tag; /* element type of the pass's per-slot diagonal tables:
+                          0 none, 1 FP64 pairs (at most 16 slots), 2 FP32 pairs
+                          (at most 32 slots); always the fused kernel's type */
+    int32_t n_tables;  /* ops of the pass that carry such a table */
+} jq_plan_step;
+
+/* The steps jq_apply_circuit runs for these gates (host only, no device
+ * work): out[0..min(max, *n_steps)-1] receives them (out may be NULL with
+ * max = 0 to count).  Validation and errors as jq_plan_schedule. */
+int jq_plan_steps(int n_qubits, int enc, const jq_gate *gates, size_t count, const jq_exec_opts *opts,
+                  jq_plan_step *out, size_t max, size_t *n_steps);
 
 /* ---- reductions (FP64 whatever the encoding) ------------------------ */
 

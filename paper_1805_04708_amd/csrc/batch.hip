@@ -568,7 +568,7 @@ bool plan_tiles(jq_batch* b, size_t i, std::vector<FPass>& passes, std::vector<F
         cfg.k_reg = b->enc == JQ_C128 ? TileShape<double>::K : TileShape<float>::K;
         cfg.max_ops = 48;
         cfg.always_pass = true;
-        cfg.f32_table = b->enc == JQ_C64;
+        cfg.table_elem = b->enc == JQ_C64 ? 4 : 8;
         Plan plan = make_plan(b->ops_host[i], cfg);
         bool ok = true;
         for (const Step& st : plan.steps) ok = ok && st.fused;
@@ -576,6 +576,7 @@ bool plan_tiles(jq_batch* b, size_t i, std::vector<FPass>& passes, std::vector<F
         if (ok) {
             for (const Step& st : plan.steps) {
                 FPass p = st.pass;
+                check_table_tag(p, b->enc == JQ_C128 ? dg_table_tag<double>() : dg_table_tag<float>());
                 p.ops = reinterpret_cast<const FOp*>((uintptr_t)st.first_fop);
                 b->tile_passes[i].push_back(p);
             }

@@ -332,9 +332,9 @@ __device__ __forceinline__ void diag_op(Cx<R> (&a)[1 << K], const FOp* op, uint6
 // A group of uncontrolled one-qubit diagonals: one factor per thread, the
 // product of the lane components (chosen per lane) and of the components
 // on index bits outside the tile (the same in every lane, from the tile
-// base, formed in FP64 once per wave); with slot = 1 the register
-// components come as a table of their product per slot, in the kernel's
-// precision.
+// base, formed in FP64 once per wave); the register components come as a
+// table of their product per slot, in the kernel's precision (slot holds
+// the table's tag; the launcher has checked that it is R's).
 template <typename R, int K>
 __device__ __forceinline__ void dgroup_op(Cx<R> (&a)[1 << K], const FOp* op, int lane, uint64_t ubase) {
     const int n = op->n_od;
@@ -352,8 +352,8 @@ __device__ __forceinline__ void dgroup_op(Cx<R> (&a)[1 << K], const FOp* op, int
         const Cx<R> d1{(R)op->od_m[4 * c + 2], (R)op->od_m[4 * c + 3]};
         t = cmul(t, csel(b, d1, d0));
     }
-    if constexpr (sizeof(R) == 4 ? K <= 5 : K <= 4) {
-        if (op->slot) {
+    if constexpr ((1 << K) <= (sizeof(R) == 4 ? kDgSlotsF32 : kDgSlotsF64)) {
+        if (op->slot == dg_table_tag<R>()) {
             // register components: the planner's product per slot, float
             // pairs for complex64, double pairs otherwise
             const R* tab = reinterpret_cast<const R*>(op->m);

@@ -101,10 +101,20 @@ enum FOpKind : int32_t {
     F_CSHIFT = 11,      // two-byte code: add the integer m[v] to the phase code (v = selector value),
                         // run as the masked-add terms cs_*
     F_DGROUP = 12,      // product of uncontrolled one-qubit diagonals: n_od on lane bits and
-                        // index bits outside the tile, and (slot = 1) those on register slots as
-                        // their product per slot s at m[2s], m[2s+1] (double pairs, at most 16
-                        // slots) or, for complex64, as float pairs over m's bytes (at most 32)
+                        // index bits outside the tile, and those on register slots as their
+                        // product per slot s, a table whose element type slot names
+                        // (kDgTableF64: double pairs at m[2s], m[2s+1], at most 16 slots;
+                        // kDgTableF32: float pairs over m's bytes, at most 32; 0: no table)
 };
+
+// F_DGROUP register tables: the tag in FOp::slot and the slots each holds
+constexpr int kDgTableF64 = 1;
+constexpr int kDgTableF32 = 2;
+constexpr int kDgSlotsF64 = 16;
+constexpr int kDgSlotsF32 = 32;
+// the tag of the tables a kernel computing in R reads
+template <typename R>
+constexpr int dg_table_tag() { return sizeof(R) == 4 ? kDgTableF32 : kDgTableF64; }
 
 
 constexpr int kMaxOdiag = 8;  // components of one F_DGROUP op
@@ -146,8 +156,13 @@ struct FPass {
     int32_t n_tile;
     int32_t tile_sorted[kMaxTileBits];
     int32_t n_ops;
+    int32_t table_tag;   // the tag of the pass's F_DGROUP register tables (0: none)
     const FOp* ops;      // device pointer
 };
+
+// Host check before a fused pass runs in a kernel computing in R: its
+// register tables must be in R's element type (throws JQ_EINVAL).
+void check_table_tag(const FPass& p, int tag_of_kernel);
 
 // One step of an execution plan: a single op through a per-gate kernel, or
 // a fused pass over [first_fop, first_fop + n_fops) of the plan's FOp list.
@@ -183,9 +198,10 @@ struct PlanConfig {
     // time of a pass's streaming in units of one op's arithmetic (weighs
     // fewer passes against more ops in the search)
     double pass_ops = 18.0;
-    // complex64 kernels: per-slot diagonal tables are float pairs (up to 32
-    // slots in FOp::m) instead of double pairs (up to 16)
-    bool f32_table = false;
+    // bytes of the fused kernel's real type: 8 (double pairs in per-slot
+    // diagonal tables, up to 16 slots) or 4 (complex64: float pairs, up to
+    // 32); make_plan rejects other values
+    int table_elem = 8;
 };
 
 struct Plan {

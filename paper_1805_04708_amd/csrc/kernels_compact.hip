@@ -1205,6 +1205,7 @@ void cp_apply_block(const CompactBufs& b, int n, const FPass& pass, int k_reg, i
     ensure_lut();
     if (n < 6 + k_reg) fail(JQ_EINVAL, "compact fused pass: state smaller than a tile");
     if (fixed_lane_bits != kCpFixedLaneBits) fail(JQ_EINVAL, "compact fused pass: unsupported lane layout");
+    check_table_tag(pass, dg_table_tag<double>());
     switch (k_reg) {
         case 2: launch_cp_fused<2, kCpFixedLaneBits>(b, n, pass, keeps, st); break;
         case 3: launch_cp_fused<3, kCpFixedLaneBits>(b, n, pass, keeps, st); break;

@@ -483,6 +483,9 @@ void sv_apply_op(int enc, void* psi, int n, const GateOp& op, hipStream_t st) {
 }
 
 void sv_apply_fused(int enc, void* psi, int n, const FPass& pass, int k_reg, int fixed_lane_bits, hipStream_t st) {
+    check_table_tag(pass, enc == JQ_C128 ? dg_table_tag<double>() : dg_table_tag<float>());
+    if ((1 << k_reg) > (enc == JQ_C128 ? kDgSlotsF64 : kDgSlotsF32) && pass.table_tag != 0)
+        fail(JQ_EINVAL, "fused pass: diagonal table smaller than the register tile");
     if (enc == JQ_C128) {
         if (fixed_lane_bits != 3) fail(JQ_EINVAL, "c128 fused pass expects 3 fixed lane bits");
         fused_dispatch<double, 3>((double2*)psi, n, pass, k_reg, st);

@@ -459,6 +459,11 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step
         if (on_step) on_step(plan);
     };
     const int n = cfg.n, F = cfg.fixed_lane_bits, K = cfg.k_reg;
+    if (cfg.table_elem != 4 && cfg.table_elem != 8) fail(JQ_EINVAL, "planner: table element must be 4 or 8 bytes");
+    // per-slot tables of register diagonals: in the fused kernel's element
+    // type, when all 2^K slots fit one op
+    const int table_tag = cfg.table_elem == 4 ? kDgTableF32 : kDgTableF64;
+    const bool reg_table = (1 << K) <= (cfg.table_elem == 4 ? kDgSlotsF32 : kDgSlotsF64);
     const bool can_fuse = cfg.fuse && K >= 1 && K >= cfg.fixed_reg_bits && n >= 6 + K && 6 + K <= kMaxTileBits;
     if (!can_fuse) {
         for (const auto& op : ops) {
@@ -555,7 +560,7 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step
             merge_same_target(L.pops);
         }
         L.n_ops = 0;
-        for (const auto& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain, K <= (cfg.f32_table ? 5 : 4)))
+        for (const auto& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain, reg_table))
             L.n_ops += it.pop >= 0 && is_swap(L.pops[it.pop].op) ? 3 : 1;
         return L;
     };
@@ -671,40 +676,47 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step
         s.fused = true;
         s.k_reg = K;
         s.pass = L.p;
+        s.pass.table_tag = 0;
         const FPass& p = s.pass;
         s.first_fop = plan.fops.size();
         int n_ops = 0;
         uint64_t reg_bits = 0;
         for (int j = 0; j < K; ++j) reg_bits |= 1ull << p.reg_q[j];
-        for (const PassItem& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain, K <= (cfg.f32_table ? 5 : 4))) {
+        for (const PassItem& it : emit_order(L.pops, reg_bits | lane_bits_of(p), reg_bits, cfg.code_domain, reg_table)) {
             if (it.pop < 0) {
                 FOp f{};
                 f.kind = F_DGROUP;
                 f.sel_reg[0] = f.sel_reg[1] = f.sel_glob[0] = f.sel_glob[1] = -1;
                 // register components: their product per slot
-                cd table[32];
+                cd table[kDgSlotsF32];
                 for (auto& e : table) e = {1.0, 0.0};
                 for (int g : it.group) {
                     const GateOp& d = L.pops[g].op;
                     for (int j = 0; j < K; ++j) {
                         if (p.reg_q[j] != d.t0) continue;
-                        f.slot = 1;
+                        // emit_order groups register diagonals only when the
+                        // table holds every slot
+                        if (!reg_table) fail(JQ_EINVAL, "planner: register table exceeds its capacity");
+                        f.slot = table_tag;
                         for (int s = 0; s < (1 << K); ++s) table[s] = cmulh(table[s], d.m[(s >> j) & 1]);
                     }
                 }
-                if (f.slot && cfg.f32_table) {
-                    float t32[64];
+                if (f.slot == kDgTableF32) {
+                    float t32[2 * kDgSlotsF32];
                     for (int s = 0; s < (1 << K); ++s) {
                         t32[2 * s] = (float)table[s].re;
                         t32[2 * s + 1] = (float)table[s].im;
                     }
+                    static_assert(sizeof(t32) <= sizeof(FOp::m), "float table fits the op");
                     std::memcpy(f.m, t32, sizeof(float) * 2 * (1 << K));
-                } else if (f.slot) {
+                } else if (f.slot == kDgTableF64) {
+                    static_assert(2 * kDgSlotsF64 <= sizeof(FOp::m) / sizeof(double), "double table fits the op");
                     for (int s = 0; s < (1 << K); ++s) {
                         f.m[2 * s] = table[s].re;
                         f.m[2 * s + 1] = table[s].im;
                     }
                 }
+                if (f.slot) s.pass.table_tag = f.slot;
                 f.n_od = 0;
                 for (int g : it.group) {
                     const GateOp& d = L.pops[g].op;
@@ -753,6 +765,11 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step
         emit(std::move(s));
     }
     return plan;
+}
+
+void check_table_tag(const FPass& p, int tag_of_kernel) {
+    if (p.table_tag != 0 && p.table_tag != tag_of_kernel)
+        fail(JQ_EINVAL, "fused pass: its diagonal tables are not in the kernel's element type");
 }
 
 }  // namespace jq

@@ -188,7 +188,7 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
     // (complex64: half the bytes, as many instructions per op); the
     // two-byte code's decoding passes are taken as complex128's
     c.pass_ops = enc == JQ_C64 ? 6.0 : 19.0;
-    c.f32_table = enc == JQ_C64;
+    c.table_elem = enc == JQ_C64 ? 4 : 8;
     // the tile-slot search costs about 0.1 ms of host time per pass: worth
     // it once a pass streams 2 GiB or more
     c.search_rounds = std::ldexp((double)bytes_per_amp(enc), n) >= std::ldexp(1.0, 30) ? 2 : 0;
@@ -201,6 +201,11 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
         if (opts->fusion == 1) c.fuse = false;
         else if (opts->fusion >= 2) c.k_reg = std::min(opts->fusion, c.code_domain ? 7 : k_max);
         if (opts->max_ops > 0) c.max_ops = std::min(opts->max_ops, 256);
+        if (opts->search == JQ_SEARCH_ON) c.search_rounds = 2;
+        else if (opts->search == JQ_SEARCH_OFF) c.search_rounds = 0;
+        else if (opts->search != JQ_SEARCH_AUTO) fail(JQ_EINVAL, "jq_exec_opts: bad search");
+        for (int r : opts->reserved)
+            if (r != 0) fail(JQ_EINVAL, "jq_exec_opts: reserved fields must be zero");
     }
     if (c.code_domain) {
         c.absorb = false;
@@ -451,6 +456,29 @@ GateOp projector(int n, int q, int v, double f) {
 
 void check_qubit(const jq_state* s, int q, const char* who) {
     if (q < 0 || q >= s->n) fail(JQ_EINVAL, std::string(who) + ": qubit out of range");
+}
+
+// Host-only planning of a circuit for the schedule and step reports:
+// validates, lowers, and plans; src[k] is the input index of op k.
+Plan plan_host(const char* who, int n_qubits, int enc, const jq_gate* gates, size_t count,
+               const jq_exec_opts* opts, std::vector<int32_t>* src_out) {
+    const std::string w(who);
+    if (n_qubits < 1 || n_qubits > JQ_MAX_QUBITS) fail(JQ_EINVAL, w + ": N must be in [1, 63]");
+    if (enc != JQ_C128 && enc != JQ_C64 && enc != JQ_COMPACT) fail(JQ_EINVAL, w + ": bad encoding");
+    if (count && !gates) fail(JQ_EINVAL, w + ": null gates");
+    std::vector<GateOp> ops;
+    std::vector<int32_t> src;
+    for (size_t i = 0; i < count; ++i) {
+        if (gates[i].nq == 0) continue;  // identity
+        try {
+            ops.push_back(canonicalize(gates[i], n_qubits));
+        } catch (const Error& e) {
+            fail(e.code, "gate " + std::to_string(i) + ": " + e.what());
+        }
+        src.push_back((int32_t)i);
+    }
+    if (src_out) *src_out = std::move(src);
+    return make_plan(ops, plan_config(n_qubits, enc, opts));
 }
 
 }  // namespace jq
@@ -747,25 +775,42 @@ int jq_measure(jq_state* s, int qubit, double u, int* outcome, double* p1_out) {
     });
 }
 
+int jq_plan_steps(int n_qubits, int enc, const jq_gate* gates, size_t count, const jq_exec_opts* opts,
+                  jq_plan_step* out, size_t max, size_t* n_steps) {
+    return guarded([&] {
+        if (!n_steps) fail(JQ_EINVAL, "jq_plan_steps: null n_steps");
+        if (max && !out) fail(JQ_EINVAL, "jq_plan_steps: null output");
+        const Plan plan = plan_host("jq_plan_steps", n_qubits, enc, gates, count, opts, nullptr);
+        for (size_t k = 0; k < plan.steps.size() && k < max; ++k) {
+            const Step& st = plan.steps[k];
+            jq_plan_step& o = out[k];
+            std::memset(&o, 0, sizeof(o));
+            o.fused = st.fused ? 1 : 0;
+            o.n_gates = (int32_t)st.gates.size();
+            for (int j = 0; j < 8; ++j) o.reg_q[j] = -1;
+            for (int b = 0; b < 6; ++b) o.lane_q[b] = -1;
+            if (!st.fused) continue;
+            o.k_reg = st.k_reg;
+            for (int j = 0; j < st.k_reg && j < 8; ++j) o.reg_q[j] = st.pass.reg_q[j];
+            for (int b = 0; b < 6; ++b) o.lane_q[b] = st.pass.lane_q[b];
+            o.n_ops = st.pass.n_ops;
+            o.table_tag = st.pass.table_tag;
+            for (int i = 0; i < st.pass.n_ops; ++i) {
+                const FOp& f = plan.fops[st.first_fop + i];
+                if (f.kind == F_DGROUP && f.slot != 0) ++o.n_tables;
+            }
+        }
+        *n_steps = plan.steps.size();
+    });
+}
+
 int jq_plan_schedule(int n_qubits, int enc, const jq_gate* gates, size_t count, const jq_exec_opts* opts,
                      int32_t* order, int32_t* block_len, int32_t* block_fused, size_t* n_blocks) {
     return guarded([&] {
-        if (n_qubits < 1 || n_qubits > JQ_MAX_QUBITS) fail(JQ_EINVAL, "jq_plan_schedule: N must be in [1, 63]");
-        if (enc != JQ_C128 && enc != JQ_C64 && enc != JQ_COMPACT) fail(JQ_EINVAL, "jq_plan_schedule: bad encoding");
         if (!n_blocks) fail(JQ_EINVAL, "jq_plan_schedule: null n_blocks");
         if (count && (!gates || !order || !block_len)) fail(JQ_EINVAL, "jq_plan_schedule: null array");
-        std::vector<GateOp> ops;
         std::vector<int32_t> src;
-        for (size_t i = 0; i < count; ++i) {
-            if (gates[i].nq == 0) continue;  // identity
-            try {
-                ops.push_back(canonicalize(gates[i], n_qubits));
-            } catch (const Error& e) {
-                fail(e.code, "gate " + std::to_string(i) + ": " + e.what());
-            }
-            src.push_back((int32_t)i);
-        }
-        const Plan plan = make_plan(ops, plan_config(n_qubits, enc, opts));
+        const Plan plan = plan_host("jq_plan_schedule", n_qubits, enc, gates, count, opts, &src);
         size_t k = 0, b = 0;
         for (const auto& step : plan.steps) {
             for (int g : step.gates) order[k++] = src[g];

@@ -21,6 +21,7 @@ JQ_C128, JQ_C64, JQ_COMPACT = 0, 1, 2
 JQ_INIT_ZERO, JQ_INIT_UNIFORM, JQ_INIT_BASIS = 0, 1, 2
 JQ_DENSE, JQ_DIAGONAL, JQ_PERM_X = 0, 1, 2
 JQ_COMPACT_PER_GATE, JQ_COMPACT_PER_BLOCK = 0, 1
+JQ_SEARCH_AUTO, JQ_SEARCH_ON, JQ_SEARCH_OFF = 0, 1, 2
 JQ_MAX_CONTROLS = 4
 ENCODINGS = {"c128": JQ_C128, "c64": JQ_C64, "compact": JQ_COMPACT}
 
@@ -39,7 +40,13 @@ class Gate(ctypes.Structure):
 
 class ExecOpts(ctypes.Structure):
     _fields_ = [("fusion", ctypes.c_int32), ("compact_mode", ctypes.c_int32), ("max_ops", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("search", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class PlanStep(ctypes.Structure):
+    _fields_ = [("fused", ctypes.c_int32), ("k_reg", ctypes.c_int32), ("reg_q", ctypes.c_int32 * 8),
+                ("lane_q", ctypes.c_int32 * 6), ("n_gates", ctypes.c_int32), ("n_ops", ctypes.c_int32),
+                ("table_tag", ctypes.c_int32), ("n_tables", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -90,6 +97,9 @@ SIGNATURES = {
                                         ctypes.POINTER(ExecOpts), ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "jq_plan_steps": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Gate), ctypes.c_size_t,
+                                     ctypes.POINTER(ExecOpts), ctypes.POINTER(PlanStep), ctypes.c_size_t,
+                                     ctypes.POINTER(ctypes.c_size_t)]),
     "jq_norm": (ctypes.c_int, [_VP, _DP]),
     "jq_probabilities": (ctypes.c_int, [_VP, _IP, ctypes.c_int, _DP]),
     "jq_expectations": (ctypes.c_int, [_VP, _DP, _DP, _DP]),
@@ -178,18 +188,33 @@ def gates(circuit):
     return arr, len(circuit)
 
 
-def exec_opts(fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0):
+def exec_opts(fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0, search=JQ_SEARCH_AUTO):
     o = ExecOpts()
-    o.fusion, o.compact_mode, o.max_ops = fusion, compact_mode, max_ops
+    o.fusion, o.compact_mode, o.max_ops, o.search = fusion, compact_mode, max_ops, search
     return o
 
 
-def plan_schedule(n, enc, circuit, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0):
+def plan_steps(n, enc, circuit, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0, search=JQ_SEARCH_AUTO):
+    """Host-only list of the steps jq_apply_circuit runs (jq_plan_steps), as dicts."""
+    arr, cnt = circuit if isinstance(circuit, tuple) else gates(circuit)
+    opts = exec_opts(fusion, compact_mode, max_ops, search)
+    n_steps = ctypes.c_size_t()
+    check(lib().jq_plan_steps(n, ENCODINGS.get(enc, enc), arr, cnt, ctypes.byref(opts), None, 0,
+                              ctypes.byref(n_steps)))
+    out = (PlanStep * max(1, n_steps.value))()
+    check(lib().jq_plan_steps(n, ENCODINGS.get(enc, enc), arr, cnt, ctypes.byref(opts), out, n_steps.value,
+                              ctypes.byref(n_steps)))
+    return [{"fused": bool(st.fused), "k_reg": st.k_reg, "reg_q": list(st.reg_q[:st.k_reg]),
+             "lane_q": list(st.lane_q), "n_gates": st.n_gates, "n_ops": st.n_ops, "table_tag": st.table_tag,
+             "n_tables": st.n_tables} for st in out[:n_steps.value]]
+
+
+def plan_schedule(n, enc, circuit, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0, search=JQ_SEARCH_AUTO):
     """Host-only schedule of jq_apply_circuit: (order, block_len, block_fused),
     order being input gate indices in the order applied, split into
     consecutive blocks of block_len gates (fused tile pass or single gate)."""
     arr, cnt = circuit if isinstance(circuit, tuple) else gates(circuit)
-    opts = exec_opts(fusion, compact_mode, max_ops)
+    opts = exec_opts(fusion, compact_mode, max_ops, search)
     m = max(1, cnt)
     order = np.zeros(m, dtype=np.int32)
     blen = np.zeros(m, dtype=np.int32)
@@ -280,10 +305,10 @@ class State:
                                   _dp(m) if m is not None else None))
         return self
 
-    def apply_circuit(self, circuit, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0):
+    def apply_circuit(self, circuit, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0, search=JQ_SEARCH_AUTO):
         """circuit: list of named gates, or (Gate array, count) from gates()."""
         arr, cnt = circuit if isinstance(circuit, tuple) else gates(circuit)
-        opts = exec_opts(fusion, compact_mode, max_ops)
+        opts = exec_opts(fusion, compact_mode, max_ops, search)
         check(lib().jq_apply_circuit(self.h, arr, cnt, ctypes.byref(opts)))
         return self
 

@@ -57,6 +57,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(jq.Gate) == 40 + 32 * 8
     assert jq.Gate.m.offset == 40
     assert ctypes.sizeof(jq.ExecOpts) == 32
+    assert jq.ExecOpts.search.offset == 12
+    assert ctypes.sizeof(jq.PlanStep) == 4 * (2 + 8 + 6 + 4)
     assert ctypes.sizeof(jq.Circuit) == 24
 
 

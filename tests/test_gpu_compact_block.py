@@ -31,19 +31,19 @@ def code_diffs(b0, b1, o0, o1):
     return d0, d1
 
 
-def oracle_blocks(n, circ, start, fusion=0):
-    order, blen, fused = jq.plan_schedule(n, "compact", circ, fusion=fusion, compact_mode=PER_BLOCK)
+def oracle_blocks(n, circ, start, fusion=0, search=jq.JQ_SEARCH_AUTO):
+    order, blen, fused = jq.plan_schedule(n, "compact", circ, fusion=fusion, compact_mode=PER_BLOCK, search=search)
     st = start.run([circ[i] for i in order], blocks=[int(b) for b in blen])
     return st, fused
 
 
-def gpu_blocks(n, circ, fusion=0, init=None, codes=None):
+def gpu_blocks(n, circ, fusion=0, init=None, codes=None, search=jq.JQ_SEARCH_AUTO):
     with jq.State(n, "compact") as s:
         if init is not None:
             s.init(init)
         if codes is not None:
             s.write_codes(*codes)
-        s.apply_circuit(circ, fusion=fusion, compact_mode=PER_BLOCK)
+        s.apply_circuit(circ, fusion=fusion, compact_mode=PER_BLOCK, search=search)
         b0, b1, rng = s.codes()
         amps = s.amplitudes()
     return b0, b1, rng, amps
@@ -62,13 +62,15 @@ def test_per_block_random_circuit_matches_oracle(n, fusion):
     assert 1 - f_gpu <= 2 * (1 - f_or) + 1e-12, (f_gpu, f_or)
 
 
+@pytest.mark.parametrize("search", [jq.JQ_SEARCH_AUTO, jq.JQ_SEARCH_ON])
 @pytest.mark.parametrize("n", [10, 14])
-def test_per_block_haar_layers_codes_identical(n):
-    # Haar U(2) and CZ: no value is placed on a rounding tie on purpose
-    circ = W.layered_u2_cz(n, 3, seed=n)
-    st, fused = oracle_blocks(n, circ, O.CompactState.encode(O.zero_state(n), n))
+def test_per_block_haar_layers_codes_identical(n, search):
+    # Haar U(2) and CZ: no value is placed on a rounding tie on purpose; with
+    # the search forced on, the blocks are those a 2^29-amplitude state gets
+    circ = W.layered_u2_cz(n, 3 if search == jq.JQ_SEARCH_AUTO else 8, seed=n)
+    st, fused = oracle_blocks(n, circ, O.CompactState.encode(O.zero_state(n), n), search=search)
     assert fused.any()
-    b0, b1, rng, amps = gpu_blocks(n, circ)
+    b0, b1, rng, amps = gpu_blocks(n, circ, search=search)
     d0, d1 = code_diffs(b0, b1, st.b0, st.b1)
     assert np.mean((d0 == 0) & (d1 == 0)) >= 1 - 1e-4
     assert np.allclose(rng, st.rng, rtol=1e-12, atol=0)

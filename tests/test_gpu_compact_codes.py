@@ -21,7 +21,7 @@ def _need_gpu():
     jq.lib()
 
 
-def run_both(n, circ, init=None, codes=None):
+def run_both(n, circ, init=None, codes=None, search=jq.JQ_SEARCH_AUTO):
     out = []
     for fusion in (0, 1):
         with jq.State(n, "compact") as s:
@@ -29,7 +29,7 @@ def run_both(n, circ, init=None, codes=None):
                 s.init(init)
             if codes is not None:
                 s.write_codes(*codes)
-            s.apply_circuit(circ, fusion=fusion)
+            s.apply_circuit(circ, fusion=fusion, search=search)
             out.append(s.codes())
     return out
 
@@ -38,9 +38,12 @@ def assert_same(a, b):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
+@pytest.mark.parametrize("search", [jq.JQ_SEARCH_AUTO, jq.JQ_SEARCH_ON])
 @pytest.mark.parametrize("n", [8, 12, 15])
-def test_rz_cnot_chain_bit_identical(n):
-    fused, single = run_both(n, W.rz_cnot_chain(n, 3, seed=n), init=jq.JQ_INIT_UNIFORM)
+def test_rz_cnot_chain_bit_identical(n, search):
+    # with the search forced on: the code passes a 2^29-code state gets
+    layers = 3 if search == jq.JQ_SEARCH_AUTO else 12
+    fused, single = run_both(n, W.rz_cnot_chain(n, layers, seed=n), init=jq.JQ_INIT_UNIFORM, search=search)
     assert_same(fused, single)
 
 
@@ -68,8 +71,9 @@ def test_controls_ties_and_every_code_op():
     b1 = rng.integers(-128, 128, 1 << n).astype(np.int8)
     b0[rng.random(1 << n) < 0.1] = -128
     b1[b0 == -128] = 0
-    fused, single = run_both(n, circ, codes=(b0, b1, (0.01, 0.3)))
-    assert_same(fused, single)
+    for search in (jq.JQ_SEARCH_AUTO, jq.JQ_SEARCH_ON):
+        fused, single = run_both(n, circ, codes=(b0, b1, (0.01, 0.3)), search=search)
+        assert_same(fused, single)
     order, blen, fused_flags = jq.plan_schedule(n, "compact", circ)
     assert fused_flags.any()
 

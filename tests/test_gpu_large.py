@@ -1,14 +1,20 @@
-"""GPU checks at the workload sizes: the 30-qubit complex128 layered circuit in
-the benchmark's launch configuration, and 256 GiB states (N=34 complex128,
-N=37 two-byte code).  The oracle cannot hold these states, so the checks use
-outputs it can compute one by one (product-state amplitudes through its own
-gate table) and properties that hold at any size (a circuit followed by its
+"""GPU checks at the workload sizes: the 30-qubit layered circuit in the
+benchmark's launch configuration, the first sizes whose plans use the
+planner's large-state steps by default (1 GiB states: N=26 complex128, N=27
+complex64, every amplitude against the oracle), and 256 GiB states (N=34
+complex128, N=37 two-byte code).  At 30 qubits and above the oracle cannot
+hold the state in its test budget, so the checks use outputs it can compute
+one by one (product-state amplitudes through its own gate table), the
+per-gate kernels (no planner; each checked against the oracle on every
+target) and properties that hold at any size (a circuit followed by its
 inverse returns |0...0>, norms, closed-form GHZ and uniform states)."""
 import math
+import threading
 
 import numpy as np
 import pytest
 
+from oracle import core as O
 from oracle import gates as OG
 from paper_1805_04708_amd import jq
 from paper_1805_04708_amd import workloads as W
@@ -44,6 +50,104 @@ def inverse(circ):
         else:
             raise ValueError(name)
     return out
+
+
+def chunked_compare(a, b, n, chunk=1 << 24):
+    """(||a - b||, ||b||) over two states read back in chunks: a and b are
+    states, or a state and a full host array."""
+    d2 = r2 = 0.0
+    for first in range(0, 1 << n, chunk):
+        x = a.amplitudes(first, chunk) if hasattr(a, "amplitudes") else a[first:first + chunk]
+        y = b.amplitudes(first, chunk) if hasattr(b, "amplitudes") else b[first:first + chunk]
+        d2 += float(np.sum(np.abs(x - y) ** 2))
+        r2 += float(np.sum(np.abs(y) ** 2))
+    return math.sqrt(d2), math.sqrt(r2)
+
+
+@pytest.mark.timeout(900)
+def test_layered_circuit_at_the_first_searched_sizes_matches_the_oracle():
+    # the smallest states on which the planner's large-state steps are on by
+    # default (1 GiB: N=26 complex128, N=27 complex64), four layers of the
+    # layered workload, every amplitude against the oracle; the oracle runs
+    # in threads while the GPU works (its C loops release the interpreter)
+    cases = [(26, "c128", 1e-12), (27, "c64", None)]
+    circs = {n: W.layered_u2_cz(n, 4, seed=900 + n) for n, _, _ in cases}
+    ref = {}
+
+    def oracle(n):
+        ref[n] = O.run(O.zero_state(n), n, circs[n])
+
+    threads = {n: threading.Thread(target=oracle, args=(n,)) for n, _, _ in cases}
+    for t in threads.values():
+        t.start()
+    try:
+        for n, enc, tol in cases:
+            key = lambda st: [(x["reg_q"], x["lane_q"], x["n_gates"]) for x in st]
+            assert key(jq.plan_steps(n, enc, circs[n])) == key(jq.plan_steps(n, enc, circs[n],
+                                                                               search=jq.JQ_SEARCH_ON))
+            with jq.State(n, enc) as s:
+                s.apply_circuit(circs[n])
+                got = s.amplitudes()
+            threads[n].join()
+            err = O.rel_l2(got, ref[n])
+            limit = tol if tol else 2e-6 * max(1.0, math.sqrt(len(circs[n]) / 100.0))
+            print(f"N={n} {enc} {len(circs[n])} gates: rel L2 vs oracle {err:.3e}", flush=True)
+            assert err <= limit, (n, enc, err)
+            del got
+            ref.pop(n)
+    finally:
+        for t in threads.values():
+            t.join()
+
+
+@pytest.mark.timeout(600)
+def test_n30_headline_circuit_fused_equals_per_gate_and_c64_error():
+    # the 40-layer headline circuit (1800 gates) at its own size: the fused
+    # passes of the searched plan against one kernel per gate (no planner;
+    # every per-gate kernel is checked against the oracle on every target),
+    # and complex64's error against complex128
+    n = 30
+    if free_gib() < 41:
+        pytest.skip("needs 40 GiB of free HBM")
+    circ = W.layered_u2_cz(n, 40, seed=2018)
+    with jq.State(n, "c128") as fused:
+        fused.apply_circuit(circ)
+        with jq.State(n, "c128") as single:
+            single.apply_circuit(circ, fusion=1)
+            d, r = chunked_compare(fused, single, n)
+        print(f"N=30 fused vs per gate: rel L2 {d / r:.3e}", flush=True)
+        assert d / r <= 1e-12, d / r
+        with jq.State(n, "c64") as low:
+            low.apply_circuit(circ)
+            d64, _ = chunked_compare(low, fused, n)
+        print(f"N=30 complex64 vs complex128: rel L2 {d64 / r:.3e}", flush=True)
+        assert d64 / r <= 2e-6 * math.sqrt(len(circ) / 100.0), d64 / r
+        assert abs(fused.norm() - 1.0) < 1e-12
+
+
+def test_n30_c64_rz_cnot_chain_closed_form():
+    # 20 layers of RZ and the CNOT chain from the uniform state in
+    # complex64 (one-qubit diagonals on register qubits run as FP32 tables):
+    # each amplitude is 2^-15 times the product of the RZ entries met along
+    # its source index's path, to FP32 rounding
+    n = 30
+    circ = W.rz_cnot_chain(n, 20, seed=30)
+    with jq.State(n, "c64") as s:
+        s.init(jq.JQ_INIT_UNIFORM)
+        s.apply_circuit(circ)
+        src = np.random.default_rng(301).integers(0, 1 << n, 48)
+        worst = 0.0
+        for j in [int(x) for x in src] + [0, (1 << n) - 1, (1 << 29) | 4321]:
+            i, amp = j, complex(2.0 ** (-n / 2))
+            for name, q, p in circ:
+                if name == "RZ":
+                    amp *= OG.matrix("RZ", p)[(i >> q[0]) & 1, (i >> q[0]) & 1]
+                elif (i >> q[0]) & 1:
+                    i ^= 1 << q[1]
+            got = s.amplitudes(i, 1)[0]
+            worst = max(worst, abs(got - amp) / abs(amp))
+        assert worst < 1e-5, worst
+        assert abs(s.norm() - 1.0) < 1e-5
 
 
 def test_n30_layer_amplitudes_one_by_one():

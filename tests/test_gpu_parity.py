@@ -37,7 +37,7 @@ def _need_gpu():
 TOL = {"c128": 1e-12, "c64": 2e-6}
 
 
-def run_gpu(n, enc, circuit, fusion=0, init=None):
+def run_gpu(n, enc, circuit, fusion=0, init=None, search=jq.JQ_SEARCH_AUTO):
     with jq.State(n, enc) as s:
         if isinstance(init, np.ndarray):
             s.write_amplitudes(init)
@@ -46,8 +46,15 @@ def run_gpu(n, enc, circuit, fusion=0, init=None):
         elif init == "uniform":
             s.init(jq.JQ_INIT_UNIFORM)
         if circuit:
-            s.apply_circuit(circuit, fusion=fusion)
+            s.apply_circuit(circuit, fusion=fusion, search=search)
         return s.amplitudes()
+
+
+# The planner's large-state steps (tile-slot search, register/lane split,
+# lane order) are on by default only for states of 1 GiB or more; the fused
+# tests below also run them forced on, so the plans the 30-qubit workloads
+# get are checked against the oracle at sizes it finishes in seconds.
+SEARCH = [jq.JQ_SEARCH_AUTO, jq.JQ_SEARCH_ON]
 
 
 def run_oracle(n, circuit, init=None):
@@ -170,9 +177,10 @@ def random_u4(rng):
     return tuple(flat)
 
 
+@pytest.mark.parametrize("search", SEARCH)
 @pytest.mark.parametrize("enc", ["c128", "c64"])
 @pytest.mark.parametrize("fusion", [0, 2, 3, 4, 5])
-def test_swap_in_fused_passes(enc, fusion):
+def test_swap_in_fused_passes(enc, fusion, search):
     # SWAPs (some controlled) run inside passes as three controlled X ops,
     # with diagonal gates on their qubits before and after (which must not
     # move past them) and a general two-qubit gate that stays unfused
@@ -188,7 +196,7 @@ def test_swap_in_fused_passes(enc, fusion):
             circ.append(("MAT2", (a, c), random_u4(rng)))
     psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
     psi0 /= np.linalg.norm(psi0)
-    got = run_gpu(n, enc, circ, fusion=fusion, init=psi0)
+    got = run_gpu(n, enc, circ, fusion=fusion, init=psi0, search=search)
     ref = run_oracle(n, circ, init=psi0)
     assert O.rel_l2(got, ref) <= tol(enc, len(circ)), O.rel_l2(got, ref)
 
@@ -229,19 +237,21 @@ def test_random_circuit_16_qubits(enc, fusion):
     assert O.rel_l2(got, ref) <= tol(enc, 200), O.rel_l2(got, ref)
 
 
+@pytest.mark.parametrize("search", SEARCH)
 @pytest.mark.parametrize("enc", ["c128", "c64"])
 @pytest.mark.parametrize("n,fusion", [(10, 0), (13, 0), (17, 0), (17, 3), (18, 2), (19, 5)])
-def test_layered_circuit_fused(enc, n, fusion):
+def test_layered_circuit_fused(enc, n, fusion, search):
     if enc == "c128" and fusion > 5:
         pytest.skip()
-    circ = W.layered_u2_cz(n, 3, seed=n)
-    got = run_gpu(n, enc, circ, fusion=fusion)
+    circ = W.layered_u2_cz(n, 3 if search == jq.JQ_SEARCH_AUTO else 8, seed=n)
+    got = run_gpu(n, enc, circ, fusion=fusion, search=search)
     ref = run_oracle(n, circ)
     assert O.rel_l2(got, ref) <= tol(enc, len(circ)), O.rel_l2(got, ref)
 
 
+@pytest.mark.parametrize("search", SEARCH)
 @pytest.mark.parametrize("enc", ["c128", "c64"])
-def test_fused_mixed_gates_with_controls(enc):
+def test_fused_mixed_gates_with_controls(enc, search):
     n = 15
     rng = np.random.default_rng(9)
     circ = []
@@ -265,13 +275,14 @@ def test_fused_mixed_gates_with_controls(enc):
     psi0 = rand_state(rng, n)
     ref = run_oracle(n, circ, init=psi0)
     for fusion in (0, 2, 3, 4):
-        got = run_gpu(n, enc, circ, fusion=fusion, init=psi0)
+        got = run_gpu(n, enc, circ, fusion=fusion, init=psi0, search=search)
         assert O.rel_l2(got, ref) <= tol(enc, 300), (fusion, O.rel_l2(got, ref))
 
 
+@pytest.mark.parametrize("search", SEARCH)
 @pytest.mark.parametrize("enc", ["c128", "c64"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_fused_diagonal_folding(enc, seed):
+def test_fused_diagonal_folding(enc, seed, search):
     # dense gates surrounded by runs of diagonal gates on their qubits: the
     # planner folds up to two selector qubits into each dense gate
     n = 14
@@ -294,7 +305,7 @@ def test_fused_diagonal_folding(enc, seed):
     psi0 = rand_state(rng, n)
     ref = run_oracle(n, circ, init=psi0)
     for fusion in (0, 2, 3):
-        got = run_gpu(n, enc, circ, fusion=fusion, init=psi0)
+        got = run_gpu(n, enc, circ, fusion=fusion, init=psi0, search=search)
         assert O.rel_l2(got, ref) <= tol(enc, len(circ)), (fusion, O.rel_l2(got, ref))
 
 
@@ -499,9 +510,10 @@ def test_fused_op_ring_wraps_and_grows(enc):
         assert O.rel_l2(got, ref) <= tol(enc, total), O.rel_l2(got, ref)
 
 
+@pytest.mark.parametrize("search", SEARCH)
 @pytest.mark.parametrize("enc", ["c128", "c64"])
 @pytest.mark.parametrize("n", [12, 16, 21])
-def test_one_qubit_diagonals_run_grouped(enc, n):
+def test_one_qubit_diagonals_run_grouped(enc, n, search):
     # layers of one-qubit diagonals (RZ, T, S, Z, U1) on every qubit between
     # Hadamards and a CNOT chain: in a pass, those on lane qubits and on
     # qubits outside the tile run as products, one factor per thread
@@ -519,6 +531,23 @@ def test_one_qubit_diagonals_run_grouped(enc, n):
                 circ.append((["T", "S", "Z"][k - 2], (q,), ()))
         circ += [("CNOT", (q, q + 1), ()) for q in range(n - 1)]
     psi = rand_state(rng, n)
-    got = run_gpu(n, enc, circ, init=psi)
+    got = run_gpu(n, enc, circ, init=psi, search=search)
     ref = run_oracle(n, circ, init=psi)
     assert O.rel_l2(got, ref) <= tol(enc, len(circ)), O.rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
+@pytest.mark.parametrize("n", [14, 18])
+def test_searched_plans_differ_and_match_the_oracle(enc, n):
+    # the searched plan of a deep layered circuit is not the first-come plan
+    # (else the forced runs above would test nothing new), and both give the
+    # oracle's state
+    circ = W.layered_u2_cz(n, 12, seed=40 + n) + W.rz_cnot_chain(n, 6, seed=n)
+    on = jq.plan_steps(n, enc, circ, search=jq.JQ_SEARCH_ON)
+    off = jq.plan_steps(n, enc, circ, search=jq.JQ_SEARCH_OFF)
+    assert [(s["reg_q"], s["lane_q"]) for s in on] != [(s["reg_q"], s["lane_q"]) for s in off]
+    psi = rand_state(np.random.default_rng(n), n)
+    ref = run_oracle(n, circ, init=psi)
+    for search in (jq.JQ_SEARCH_ON, jq.JQ_SEARCH_OFF):
+        got = run_gpu(n, enc, circ, init=psi, search=search)
+        assert O.rel_l2(got, ref) <= tol(enc, len(circ)), (search, O.rel_l2(got, ref))

@@ -43,9 +43,14 @@ def targets_of(g):
     return q
 
 
+SEARCH_ON = {"search": jq.JQ_SEARCH_ON}
+
+
 @pytest.mark.parametrize("n", [8, 12, 16])
 @pytest.mark.parametrize("enc,kw", [("c128", {}), ("c64", {}), ("c128", {"fusion": 2}),
-                                    ("c128", {"fusion": 5}), ("compact", {"compact_mode": PER_BLOCK})])
+                                    ("c128", {"fusion": 5}), ("compact", {"compact_mode": PER_BLOCK}),
+                                    ("c128", SEARCH_ON), ("c64", SEARCH_ON), ("compact", SEARCH_ON),
+                                    ("compact", {"compact_mode": PER_BLOCK, **SEARCH_ON})])
 def test_schedule_is_a_commuting_reordering(n, enc, kw):
     for circ in circuits(n):
         order, blen, fused = schedule(n, enc, circ, **kw)
@@ -63,7 +68,8 @@ def test_schedule_is_a_commuting_reordering(n, enc, kw):
 
 
 @pytest.mark.parametrize("enc,kw", [("c128", {}), ("c64", {}), ("c128", {"fusion": 3}),
-                                    ("compact", {"compact_mode": PER_BLOCK})])
+                                    ("compact", {"compact_mode": PER_BLOCK}), ("c128", SEARCH_ON),
+                                    ("c64", SEARCH_ON)])
 def test_fused_blocks_fit_one_tile(enc, kw):
     n = 20
     F, K = LAYOUT[enc]
@@ -257,3 +263,62 @@ def test_tile_slot_search_shortens_rz_cnot_chains():
     # the layered Haar U(2) + CZ circuit: 62 passes before the search
     _, blen, fused = schedule(n, "c128", W.layered_u2_cz(n, 40, seed=2018))
     assert all(fused) and len(blen) <= 57, len(blen)
+
+
+def test_search_switch_reaches_small_states():
+    # the large-state steps (tile-slot search, register/lane split, lane
+    # order) are on by default only for states of 1 GiB or more; the switch
+    # turns them on at any size, which changes the passes of a deep circuit
+    # at N=16, and off at any size, which reproduces the small-state plan
+    n = 16
+    circ = W.rz_cnot_chain(n, 12, seed=2) + W.layered_u2_cz(n, 6, seed=3)
+    auto = jq.plan_steps(n, "c128", circ)
+    on = jq.plan_steps(n, "c128", circ, search=jq.JQ_SEARCH_ON)
+    off = jq.plan_steps(n, "c128", circ, search=jq.JQ_SEARCH_OFF)
+    key = lambda st: [(s["fused"], s["reg_q"], s["lane_q"], s["n_gates"]) for s in st]
+    assert key(auto) == key(off)
+    assert key(on) != key(off)
+    # at N=26 (1 GiB of complex128) the default is the searched plan
+    big = 26
+    assert key(jq.plan_steps(big, "c128", circ)) == key(jq.plan_steps(big, "c128", circ, search=jq.JQ_SEARCH_ON))
+    assert key(jq.plan_steps(big, "c128", circ)) != key(jq.plan_steps(big, "c128", circ, search=jq.JQ_SEARCH_OFF))
+
+
+def test_bad_options_are_rejected():
+    circ = [("H", (0,), ())]
+    for kw in ({"search": 3}, {"search": -1}):
+        with pytest.raises(jq.JqError) as e:
+            jq.plan_schedule(10, "c128", circ, **kw)
+        assert e.value.code == jq.JQ_EINVAL
+    opts = jq.exec_opts()
+    opts.reserved[2] = 1
+    arr, cnt = jq.gates(circ)
+    n_steps = jq.ctypes.c_size_t()
+    rc = jq.lib().jq_plan_steps(10, jq.JQ_C128, arr, cnt, jq.ctypes.byref(opts), None, 0, jq.ctypes.byref(n_steps))
+    assert rc == jq.JQ_EINVAL
+
+
+# per-slot diagonal tables: (encoding, options) -> (tag, 2^K fits the op)
+TABLE_CASES = [("c128", {}, 1, True), ("c128", {"fusion": 5}, 1, False), ("c64", {}, 2, True),
+               ("c64", {"fusion": 6}, 2, False), ("compact", {"compact_mode": PER_BLOCK}, 1, True),
+               ("c128", SEARCH_ON, 1, True), ("c64", SEARCH_ON, 2, True)]
+
+
+@pytest.mark.parametrize("enc,kw,tag,fits", TABLE_CASES)
+def test_diagonal_tables_carry_the_kernel_element_type(enc, kw, tag, fits):
+    # one-qubit diagonals on register qubits run as a table of their product
+    # per slot in the fused kernel's element type (FP64 pairs for complex128
+    # and the two-byte code's decoding kernel, at most 16 slots; FP32 pairs for
+    # complex64, at most 32): where 2^K slots fit, some pass carries tables and
+    # every tag is the kernel's; where they do not, no pass carries one
+    n = 16
+    circ = W.rz_cnot_chain(n, 4, seed=11)
+    steps = [s for s in jq.plan_steps(n, enc, circ, **kw) if s["fused"]]
+    assert steps
+    for s in steps:
+        assert s["table_tag"] in (0, tag), s
+        assert (s["n_tables"] > 0) == (s["table_tag"] != 0), s
+    if fits:
+        assert any(s["n_tables"] for s in steps)
+    else:
+        assert not any(s["n_tables"] for s in steps)
