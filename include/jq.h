@@ -191,6 +191,24 @@ int jq_apply_gate(jq_state *s, int kind, const int *qubits, int nq, const int *c
  * floating-point rounding.  Asynchronous. */
 int jq_apply_circuit(jq_state *s, const jq_gate *gates, size_t count, const jq_exec_opts *opts);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * jq_apply_circuit, with the same validation, plan, kernels and results
+ * (bit for bit), except that the plan's fused-op list is staged in a fixed
+ * device workspace of JQ_NOALLOC_WORKSPACE_BYTES per GPU (held until the
+ * process ends) instead of per-state buffers, and per-launch timing
+ * (jq_profile_enable) is not recorded.  It calls no hipMalloc, hipFree or
+ * other allocating routine; the state's device must be current.
+ * JQ_EINVAL, with nothing enqueued and the state unchanged, if the plan has
+ * more fused ops than the workspace holds (jq_plan_steps gives the plan; a
+ * fused op takes 704 bytes, so about 5900 fit).  Every call on one GPU
+ * shares that GPU's workspace, which keeps the last call's ops: calls on one
+ * stream are ordered, but calls whose work overlaps on one GPU (other
+ * streams without synchronisation between them, concurrent threads) race,
+ * and the caller must serialise them.  Asynchronous. */
+#define JQ_NOALLOC_WORKSPACE_BYTES (4u << 20)
+int jq_apply_circuit_noalloc(jq_state *s, const jq_gate *gates, size_t count, const jq_exec_opts *opts);
+
 /* jq_apply_circuit with the depolarizing channel of App. A: after each gate
  * (identity gates included), every qubit q receives an X gate with
  * probability px, a Y gate with probability py or a Z gate with probability

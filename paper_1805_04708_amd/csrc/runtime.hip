@@ -137,6 +137,22 @@ void check_state(const jq_state* s) {
     if (!s) fail(JQ_EINVAL, "null state");
 }
 
+// Validate and lower a gate list (identity gates dropped).
+std::vector<GateOp> lower_circuit(const jq_state* s, const jq_gate* gates, size_t count, const char* who) {
+    if (count && !gates) fail(JQ_EINVAL, std::string(who) + ": null gates");
+    std::vector<GateOp> ops;
+    ops.reserve(count);
+    for (size_t i = 0; i < count; ++i) {
+        if (gates[i].nq == 0) continue;  // identity
+        try {
+            ops.push_back(canonicalize(gates[i], s->n));
+        } catch (const Error& e) {
+            fail(e.code, "gate " + std::to_string(i) + ": " + e.what());
+        }
+    }
+    return ops;
+}
+
 double op_bytes(const GateOp& op, int n, int enc) {
     const double bpa = bytes_per_amp(enc);
     const double touched = std::ldexp((double)op.touched(n), 0);
@@ -341,6 +357,61 @@ void apply_ops(jq_state* s, const std::vector<GateOp>& ops, const PlanConfig& cf
         if (waiting >= (flushes ? 4u : 1u) || !pl.steps.back().fused) flush(pl);
     });
     if (launched < plan.steps.size()) flush(plan);
+}
+
+// ------------------------------------------ allocation-free circuits --
+
+// Fused-op workspace of jq_apply_circuit_noalloc: one fixed array per GPU,
+// held until the process ends.  In host code its name is only a stand-in;
+// the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[JQ_NOALLOC_WORKSPACE_BYTES];
+
+// the header states the size of a fused op and how many the workspace holds
+static_assert(sizeof(FOp) == 704, "jq.h documents 704-byte fused ops");
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// The workspace's address on device dev, which must be the current device.
+FOp* noalloc_workspace(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) fail(JQ_EDEVICE, "jq_apply_circuit_noalloc: device index out of range");
+    std::call_once(g_scratch_once[dev], [dev] {
+        void* p = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = p;
+    });
+    if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev])
+        fail(JQ_EDEVICE, std::string("jq_apply_circuit_noalloc: hipGetSymbolAddress: ") +
+                             hipGetErrorString(g_scratch_err[dev]));
+    return static_cast<FOp*>(g_scratch_ptr[dev]);
+}
+
+// The whole plan first, then one copy of its fused ops into the workspace
+// and the launches; per-launch timing is skipped (it would create events).
+void apply_ops_noalloc(jq_state* s, const std::vector<GateOp>& ops, const PlanConfig& cfg) {
+    int dev = -1;
+    JQ_HIP(hipGetDevice(&dev));
+    if (dev != s->device) fail(JQ_EINVAL, "jq_apply_circuit_noalloc: the state's device must be current");
+    FOp* ws = noalloc_workspace(dev);
+    const Plan plan = make_plan(ops, cfg);
+    const size_t bytes = plan.fops.size() * sizeof(FOp);
+    if (bytes > JQ_NOALLOC_WORKSPACE_BYTES)
+        fail(JQ_EINVAL, "jq_apply_circuit_noalloc: the plan has " + std::to_string(plan.fops.size()) +
+                            " fused ops (" + std::to_string(bytes) + " bytes), the workspace holds " +
+                            std::to_string(JQ_NOALLOC_WORKSPACE_BYTES / sizeof(FOp)));
+    // pageable source: the runtime stages it before the call returns
+    if (bytes) JQ_HIP(hipMemcpyAsync(ws, plan.fops.data(), bytes, hipMemcpyHostToDevice, s->stream));
+    const bool prof = s->profiling;
+    s->profiling = false;
+    try {
+        for (const auto& step : plan.steps) run_step(s, ops, cfg, step, step.fused ? ws + step.first_fop : nullptr);
+    } catch (...) {
+        s->profiling = prof;
+        throw;
+    }
+    s->profiling = prof;
 }
 
 void do_probabilities(jq_state* s, const int* qubits, int nq, double* out_host) {
@@ -655,18 +726,16 @@ int jq_apply_gate(jq_state* s, int kind, const int* qubits, int nq, const int* c
 int jq_apply_circuit(jq_state* s, const jq_gate* gates, size_t count, const jq_exec_opts* opts) {
     return guarded([&] {
         check_state(s);
-        if (count && !gates) fail(JQ_EINVAL, "jq_apply_circuit: null gates");
-        std::vector<GateOp> ops;
-        ops.reserve(count);
-        for (size_t i = 0; i < count; ++i) {
-            if (gates[i].nq == 0) continue;  // identity
-            try {
-                ops.push_back(canonicalize(gates[i], s->n));
-            } catch (const Error& e) {
-                fail(e.code, "gate " + std::to_string(i) + ": " + e.what());
-            }
-        }
+        const std::vector<GateOp> ops = lower_circuit(s, gates, count, "jq_apply_circuit");
         apply_ops(s, ops, plan_config(s->n, s->enc, opts));  // options validated before any work
+    });
+}
+
+int jq_apply_circuit_noalloc(jq_state* s, const jq_gate* gates, size_t count, const jq_exec_opts* opts) {
+    return guarded([&] {
+        check_state(s);
+        const std::vector<GateOp> ops = lower_circuit(s, gates, count, "jq_apply_circuit_noalloc");
+        apply_ops_noalloc(s, ops, plan_config(s->n, s->enc, opts));
     });
 }
 

@@ -91,6 +91,8 @@ SIGNATURES = {
     "jq_gate_named": (ctypes.c_int, [ctypes.c_char_p, _IP, ctypes.c_int, _DP, ctypes.c_int, ctypes.POINTER(Gate)]),
     "jq_apply_gate": (ctypes.c_int, [_VP, ctypes.c_int, _IP, ctypes.c_int, _IP, ctypes.c_int, _DP]),
     "jq_apply_circuit": (ctypes.c_int, [_VP, ctypes.POINTER(Gate), ctypes.c_size_t, ctypes.POINTER(ExecOpts)]),
+    "jq_apply_circuit_noalloc": (ctypes.c_int, [_VP, ctypes.POINTER(Gate), ctypes.c_size_t,
+                                                ctypes.POINTER(ExecOpts)]),
     "jq_apply_circuit_noisy": (ctypes.c_int, [_VP, ctypes.POINTER(Gate), ctypes.c_size_t, ctypes.c_double,
                                               ctypes.c_double, ctypes.c_double, _DP, ctypes.POINTER(ExecOpts)]),
     "jq_plan_schedule": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Gate), ctypes.c_size_t,
@@ -310,6 +312,14 @@ class State:
         arr, cnt = circuit if isinstance(circuit, tuple) else gates(circuit)
         opts = exec_opts(fusion, compact_mode, max_ops, search)
         check(lib().jq_apply_circuit(self.h, arr, cnt, ctypes.byref(opts)))
+        return self
+
+    def apply_circuit_noalloc(self, circuit, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0,
+                              search=JQ_SEARCH_AUTO):
+        """apply_circuit through jq_apply_circuit_noalloc (fixed device workspace, no allocation)."""
+        arr, cnt = circuit if isinstance(circuit, tuple) else gates(circuit)
+        opts = exec_opts(fusion, compact_mode, max_ops, search)
+        check(lib().jq_apply_circuit_noalloc(self.h, arr, cnt, ctypes.byref(opts)))
         return self
 
     def apply_circuit_noisy(self, circuit, px, py, pz, u, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0):
