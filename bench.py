@@ -65,6 +65,8 @@ def parse():
                    help="comma-separated extras to run (per_target, c64, batch, serve, compact, compact_dense, "
                         "shor, aux, large), or all")
     p.add_argument("--cpu-gates", type=int, default=3, help="gates of the circuit the CPU oracle times")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="keep the built-in tuning instead of measuring it on this device first")
     p.add_argument("--copy-calibration", type=int, default=4096, metavar="MIB",
                    help="size of the plain torch device copy reported as the copy ceiling (and used to "
                         "calibrate the traffic counters); 0 skips it")
@@ -198,6 +200,17 @@ def main():
     circuit = W.layered_u2_cz(n, args.layers, seed=args.seed)
     G = len(circuit)
 
+    # the planner's register width and pass weight and the per-gate
+    # threshold, measured on this device for this state size with the
+    # workload's circuit as the tuning circuit (on a scratch state, outside
+    # the timed steps)
+    if args.no_autotune:
+        tuning = jq.tuning_get(n, args.enc)
+    else:
+        t0 = time.perf_counter()
+        tuning = jq.autotune(n, args.enc, circuit, force=True, no_cache=True)
+        tuning["seconds"] = time.perf_counter() - t0
+
     state = jq.State(n, args.enc).set_stream(stream)
     bpa = 16 if args.enc == "c128" else 8
 
@@ -251,7 +264,8 @@ def main():
         "config": {"workload": f"layered Haar-U(2) + CZ-matching circuit, N={n}, {args.enc}, "
                                f"{args.layers} layers ({G} gates), from |0...0>",
                    "n_qubits": n, "encoding": args.enc, "layers": args.layers, "gates": G,
-                   "fusion": "auto" if args.fusion == 0 else args.fusion, "seed": args.seed},
+                   "fusion": "auto" if args.fusion == 0 else args.fusion, "seed": args.seed,
+                   "tuning": tuning},
         "norm": nrm,
         "hbm_gbps_step": alg_bytes / (dt / args.steps * args.steps) / 1e9 if dt > 0 else None,
         "kernel_ms_per_step": kernel_ms / args.steps,

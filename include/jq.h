@@ -121,6 +121,82 @@ typedef struct {
     int32_t reserved[4];
 } jq_exec_opts;
 
+/* Tuning of the single-state path for one device, encoding and state size.
+ * The paper proposes combining gates into multi-qubit blocks to raise the
+ * work per byte moved (Sec. 5.2) but gives no rule for how; these are the
+ * choices the planner and the per-gate kernels make, and jq_autotune picks
+ * them by timing them on the device:
+ *  k_reg:       register bits of a fused tile pass (a lane holds 2^k_reg
+ *               amplitudes): 2..5 for JQ_C128, 2..6 for JQ_C64;
+ *  pass_ops:    the planner's weight of one more pass against one more op
+ *               in a pass (a pass's streaming time in units of one fused
+ *               op's arithmetic), in (0, 10000];
+ *  wide_target: per-gate dense and X kernels take four amplitude pairs per
+ *               thread for targets from this qubit up, one below it (0..64;
+ *               64: never);
+ *  n_qubits:    the state size the values were tuned at (0: the built-in
+ *               defaults);
+ *  source:      JQ_TUNE_DEFAULT, JQ_TUNE_MEASURED (jq_autotune in this
+ *               process), JQ_TUNE_CACHED (read from the cache file) or
+ *               JQ_TUNE_SET (jq_tuning_set);
+ *  tuned_ms, default_ms: jq_autotune's time of its tuning circuit with the
+ *               chosen values and with the built-in defaults (0 otherwise).
+ * jq_apply_circuit (and the request loop) use the values for the state's
+ * device, encoding and N when opts is NULL or opts->fusion is 0: an entry
+ * for exactly N, else, for N >= 25 (states past the last-level cache), the
+ * entry of the largest tuned size from 25 up to N, else the defaults.  The
+ * two-byte code is not tuned.  Plans depend only on (circuit, N, encoding,
+ * tuning), so a result is the same alone and in a mix as long as the tuning
+ * does not change in between. */
+#define JQ_TUNE_DEFAULT 0
+#define JQ_TUNE_MEASURED 1
+#define JQ_TUNE_CACHED 2
+#define JQ_TUNE_SET 3
+typedef struct {
+    int32_t k_reg;
+    int32_t wide_target;
+    double pass_ops;
+    int32_t n_qubits;
+    int32_t source;
+    double tuned_ms;
+    double default_ms;
+} jq_tuning;
+
+/* The tuning jq_apply_circuit uses for an N-qubit state of encoding enc on
+ * the current device (host only; with no GPU visible the device is taken as
+ * "host").  The first call in a process reads the cache file: the path in
+ * the environment variable JQ_TUNE_CACHE, else $HOME/.cache/jq/tuning.json
+ * (a missing or unreadable file counts as empty).  JQ_EINVAL for a bad N or
+ * encoding. */
+int jq_tuning_get(int n_qubits, int enc, jq_tuning *out);
+
+/* Set the tuning for N-qubit states of encoding enc on the current device
+ * for the rest of the process (host only; nothing is written to the cache
+ * file); t = NULL removes a value set before.  JQ_EINVAL if a field is out
+ * of range (the table is then unchanged) or enc is JQ_COMPACT. */
+int jq_tuning_set(int n_qubits, int enc, const jq_tuning *t);
+
+/* Measure the tuning for N-qubit states of encoding enc (JQ_C128 or JQ_C64,
+ * 10 <= N <= 34) on the current device: a scratch state of 2^N amplitudes
+ * runs a tuning circuit under each register width from 3 up and three
+ * planner weights, and the fastest set is kept if it beats the defaults
+ * (among those timed) by 2% or more; the per-gate threshold is the one
+ * that minimises the summed time of a dense gate on every target from 8 up,
+ * kept under the same 2% rule.  The tuning circuit is gates[0..count-1]
+ * (the caller's workload, validated as by jq_apply_circuit; the best
+ * register width depends on a circuit's depth and structure), or, with
+ * count = 0, ten layers of random U(2) on every qubit and CZ on a random
+ * matching.  The cache file holds one entry per device, encoding and N:
+ * the last tuning.  The result is kept for the
+ * process and merged into the cache file.  flags: JQ_TUNE_FORCE measures
+ * even when the cache file has an entry for this device, encoding and N
+ * (otherwise that entry is returned); JQ_TUNE_NO_CACHE neither reads nor
+ * writes the file.  JQ_ENOMEM if the scratch state does not fit; the
+ * device memory of the scratch state is freed before return.  Synchronous. */
+#define JQ_TUNE_FORCE 1
+#define JQ_TUNE_NO_CACHE 2
+int jq_autotune(int n_qubits, int enc, int flags, const jq_gate *gates, size_t count, jq_tuning *out);
+
 typedef struct jq_state jq_state;
 
 /* ---- state lifetime -------------------------------------------------- */

@@ -228,7 +228,9 @@ inline int bytes_per_amp(int enc) { return enc == JQ_C128 ? 16 : enc == JQ_C64 ?
 
 // state-vector (c128 / c64) launchers; psi is the device buffer
 void sv_init(int enc, void* psi, int n, int mode, uint64_t basis, hipStream_t st);
-void sv_apply_op(int enc, void* psi, int n, const GateOp& op, hipStream_t st);
+// one op by its per-gate kernel; wide_target: dense and X targets from this
+// qubit up take four pairs per thread (one below it)
+void sv_apply_op(int enc, void* psi, int n, const GateOp& op, int wide_target, hipStream_t st);
 // SHORBOX (App. A): 2^(-n_x/2) sum_x |x>|y^x mod G>, x on the n_x low qubits
 void sv_shorbox(int enc, void* psi, int n, int n_x, uint64_t G, uint64_t y, hipStream_t st);
 void sv_apply_fused(int enc, void* psi, int n, const FPass& pass, int k_reg, int fixed_lane_bits,
@@ -305,6 +307,19 @@ jq_state* state_create(int n, int enc, hipStream_t stream, bool async_alloc);
 
 // Apply canonical ops to a state (planner + kernels), asynchronously.
 void state_apply(jq_state* s, const std::vector<GateOp>& ops, const jq_exec_opts* opts);
+
+// The planner's configuration for an N-qubit state of encoding enc under
+// the caller's options (validated; NULL or fusion 0: the tuned values).
+PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts);
+// The configuration with a given register width and pass weight (tuning).
+PlanConfig plan_config_tuned(int n, int enc, int k_reg, double pass_ops);
+// Apply canonical ops under an explicit planner configuration.
+void state_apply_config(jq_state* s, const std::vector<GateOp>& ops, const PlanConfig& cfg);
+
+// Tuning of the single-state path (tuning.cpp): the values for an N-qubit
+// state of encoding enc on the current device, and the built-in defaults.
+jq_tuning tuned_for(int n, int enc);
+jq_tuning default_tuning(int enc);
 // Enqueue the FP64 squared norm into pinned host memory (no synchronisation).
 void state_norm_async(jq_state* s, double* pinned_out);
 

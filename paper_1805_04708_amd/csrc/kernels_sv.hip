@@ -323,9 +323,6 @@ Ins make_ins(uint64_t zero_bits, uint64_t ones) {
     return s;
 }
 
-// blocks for a per-gate kernel whose blocks loop over chunks of per_block
-// targets from this qubit up take four pairs per thread
-constexpr int kWideTarget = 17;
 
 // A control bit inside a 128-byte line (below qubit 3 for complex128, 4
 // for complex64) leaves parts of every line untouched: such gates keep
@@ -355,8 +352,9 @@ unsigned grid_stride_blocks(uint64_t dim) {
 
 namespace {
 
+// wide_target: targets from this qubit up take four pairs per thread
 template <typename R>
-void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, hipStream_t st) {
+void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, int wide_target, hipStream_t st) {
     const int fixed = __builtin_popcountll(op.cmask);
     switch (op.kind) {
         case OP_DENSE1: {
@@ -368,7 +366,7 @@ void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, hipStream_t st
             if (partial_lines<R>(op.cmask))
                 hipLaunchKernelGGL((k_dense1<R, 4, false>), dim3(chunk_blocks(ng, 4 * kBlock)), dim3(kBlock), 0, st,
                                    psi, ng, ins, tb, m);
-            else if (op.t0 < kWideTarget)
+            else if (op.t0 < wide_target)
                 hipLaunchKernelGGL((k_dense1<R, 1, true>), dim3(chunk_blocks(ng, kBlock)), dim3(kBlock), 0, st, psi,
                                    ng, ins, tb, m);
             else
@@ -406,7 +404,7 @@ void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, hipStream_t st
             if (partial_lines<R>(op.cmask))
                 hipLaunchKernelGGL((k_permx<R, 4, false>), dim3(chunk_blocks(ng, 4 * kBlock)), dim3(kBlock), 0, st,
                                    psi, ng, ins, tb);
-            else if (op.t0 < kWideTarget)
+            else if (op.t0 < wide_target)
                 hipLaunchKernelGGL((k_permx<R, 1, true>), dim3(chunk_blocks(ng, kBlock)), dim3(kBlock), 0, st, psi,
                                    ng, ins, tb);
             else
@@ -477,9 +475,9 @@ void sv_shorbox(int enc, void* psi, int n, int n_x, uint64_t G, uint64_t y, hipS
     JQ_HIP(hipGetLastError());
 }
 
-void sv_apply_op(int enc, void* psi, int n, const GateOp& op, hipStream_t st) {
-    if (enc == JQ_C128) apply_op_t<double>((double2*)psi, n, op, st);
-    else apply_op_t<float>((float2*)psi, n, op, st);
+void sv_apply_op(int enc, void* psi, int n, const GateOp& op, int wide_target, hipStream_t st) {
+    if (enc == JQ_C128) apply_op_t<double>((double2*)psi, n, op, wide_target, st);
+    else apply_op_t<float>((float2*)psi, n, op, wide_target, st);
 }
 
 void sv_apply_fused(int enc, void* psi, int n, const FPass& pass, int k_reg, int fixed_lane_bits, hipStream_t st) {

@@ -184,7 +184,7 @@ int kclass(const GateOp& op, int enc) {
 void run_single(jq_state* s, const GateOp& op) {
     Timed t(s, kclass(op, s->enc), op_bytes(op, s->n, s->enc));
     if (s->enc == JQ_COMPACT) cp_apply_op(compact_bufs(s), s->n, op, s->stream);
-    else sv_apply_op(s->enc, s->buf, s->n, op, s->stream);
+    else sv_apply_op(s->enc, s->buf, s->n, op, tuned_for(s->n, s->enc).wide_target, s->stream);
 }
 
 // Kernel layout per encoding: fixed lane bits F (128-byte lines for the
@@ -195,15 +195,17 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
     c.n = n;
     const bool compact = enc == JQ_COMPACT;
     c.fixed_lane_bits = compact ? kCpFixedLaneBits : enc == JQ_C64 ? 4 : 3;
-    c.k_reg = compact ? 4 : enc == JQ_C64 ? 5 : 4;
     const int k_max = compact ? 4 : enc == JQ_C64 ? 6 : 5;
     c.max_ops = 48;
     c.fuse = true;
-    // a pass's streaming time over one op's arithmetic, measured at N = 30:
-    // 4.3 ms against 0.23 ms per op (complex128), 1.25 ms against 0.20 ms
-    // (complex64: half the bytes, as many instructions per op); the
+    // register width and a pass's streaming time over one op's arithmetic:
+    // tuned per device, encoding and N, else the defaults measured at N = 30
+    // (4.3 ms against 0.23 ms per op for complex128, 1.25 ms against 0.20 ms
+    // for complex64: half the bytes, as many instructions per op); the
     // two-byte code's decoding passes are taken as complex128's
-    c.pass_ops = enc == JQ_C64 ? 6.0 : 19.0;
+    const jq_tuning tune = compact ? default_tuning(JQ_C128) : tuned_for(n, enc);
+    c.k_reg = compact ? 4 : tune.k_reg;
+    c.pass_ops = tune.pass_ops;
     c.table_elem = enc == JQ_C64 ? 4 : 8;
     // the tile-slot search costs about 0.1 ms of host time per pass: worth
     // it once a pass streams 2 GiB or more
@@ -230,6 +232,14 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
         c.pass_ops = 150.0;
         if (!(opts && opts->fusion >= 2)) c.k_reg = 7;
     }
+    while (c.fuse && c.k_reg > 2 && c.n < 6 + c.k_reg) c.k_reg--;
+    return c;
+}
+
+PlanConfig plan_config_tuned(int n, int enc, int k_reg, double pass_ops) {
+    PlanConfig c = plan_config(n, enc, nullptr);
+    c.k_reg = k_reg;
+    c.pass_ops = pass_ops;
     while (c.fuse && c.k_reg > 2 && c.n < 6 + c.k_reg) c.k_reg--;
     return c;
 }
@@ -503,6 +513,10 @@ jq_state* state_create(int n, int enc, hipStream_t stream, bool async_alloc) {
 
 void state_apply(jq_state* s, const std::vector<GateOp>& ops, const jq_exec_opts* opts) {
     apply_ops(s, ops, plan_config(s->n, s->enc, opts));
+}
+
+void state_apply_config(jq_state* s, const std::vector<GateOp>& ops, const PlanConfig& cfg) {
+    apply_ops(s, ops, cfg);
 }
 
 void state_norm_async(jq_state* s, double* pinned_out) {

@@ -22,6 +22,8 @@ JQ_INIT_ZERO, JQ_INIT_UNIFORM, JQ_INIT_BASIS = 0, 1, 2
 JQ_DENSE, JQ_DIAGONAL, JQ_PERM_X = 0, 1, 2
 JQ_COMPACT_PER_GATE, JQ_COMPACT_PER_BLOCK = 0, 1
 JQ_SEARCH_AUTO, JQ_SEARCH_ON, JQ_SEARCH_OFF = 0, 1, 2
+JQ_TUNE_DEFAULT, JQ_TUNE_MEASURED, JQ_TUNE_CACHED, JQ_TUNE_SET = 0, 1, 2, 3
+JQ_TUNE_FORCE, JQ_TUNE_NO_CACHE = 1, 2
 JQ_MAX_CONTROLS = 4
 ENCODINGS = {"c128": JQ_C128, "c64": JQ_C64, "compact": JQ_COMPACT}
 
@@ -36,6 +38,12 @@ class Gate(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nq", ctypes.c_int32), ("nc", ctypes.c_int32),
                 ("qubits", ctypes.c_int32 * 2), ("controls", ctypes.c_int32 * JQ_MAX_CONTROLS),
                 ("pad_", ctypes.c_int32), ("m", ctypes.c_double * 32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("k_reg", ctypes.c_int32), ("wide_target", ctypes.c_int32), ("pass_ops", ctypes.c_double),
+                ("n_qubits", ctypes.c_int32), ("source", ctypes.c_int32), ("tuned_ms", ctypes.c_double),
+                ("default_ms", ctypes.c_double)]
 
 
 class ExecOpts(ctypes.Structure):
@@ -102,6 +110,10 @@ SIGNATURES = {
     "jq_plan_steps": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Gate), ctypes.c_size_t,
                                      ctypes.POINTER(ExecOpts), ctypes.POINTER(PlanStep), ctypes.c_size_t,
                                      ctypes.POINTER(ctypes.c_size_t)]),
+    "jq_tuning_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Tuning)]),
+    "jq_tuning_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Tuning)]),
+    "jq_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Gate), ctypes.c_size_t,
+                                   ctypes.POINTER(Tuning)]),
     "jq_norm": (ctypes.c_int, [_VP, _DP]),
     "jq_probabilities": (ctypes.c_int, [_VP, _IP, ctypes.c_int, _DP]),
     "jq_expectations": (ctypes.c_int, [_VP, _DP, _DP, _DP]),
@@ -209,6 +221,48 @@ def plan_steps(n, enc, circuit, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_
     return [{"fused": bool(st.fused), "k_reg": st.k_reg, "reg_q": list(st.reg_q[:st.k_reg]),
              "lane_q": list(st.lane_q), "n_gates": st.n_gates, "n_ops": st.n_ops, "table_tag": st.table_tag,
              "n_tables": st.n_tables} for st in out[:n_steps.value]]
+
+
+_TUNE_SOURCES = {JQ_TUNE_DEFAULT: "default", JQ_TUNE_MEASURED: "measured", JQ_TUNE_CACHED: "cached",
+                 JQ_TUNE_SET: "set"}
+
+
+def _tuning_dict(t):
+    return {"k_reg": t.k_reg, "wide_target": t.wide_target, "pass_ops": t.pass_ops, "n_qubits": t.n_qubits,
+            "source": _TUNE_SOURCES.get(t.source, t.source), "tuned_ms": t.tuned_ms, "default_ms": t.default_ms}
+
+
+def tuning_get(n, enc):
+    """The tuning jq_apply_circuit uses for an n-qubit state (jq_tuning_get), as a dict."""
+    t = Tuning()
+    check(lib().jq_tuning_get(n, ENCODINGS.get(enc, enc), ctypes.byref(t)))
+    return _tuning_dict(t)
+
+
+def tuning_set(n, enc, k_reg=None, wide_target=None, pass_ops=None, clear=False):
+    """Override (jq_tuning_set) fields of the current tuning; clear=True removes an override."""
+    if clear:
+        check(lib().jq_tuning_set(n, ENCODINGS.get(enc, enc), None))
+        return
+    t = Tuning()
+    check(lib().jq_tuning_get(n, ENCODINGS.get(enc, enc), ctypes.byref(t)))
+    if k_reg is not None:
+        t.k_reg = k_reg
+    if wide_target is not None:
+        t.wide_target = wide_target
+    if pass_ops is not None:
+        t.pass_ops = pass_ops
+    check(lib().jq_tuning_set(n, ENCODINGS.get(enc, enc), ctypes.byref(t)))
+
+
+def autotune(n, enc, circuit=None, force=False, no_cache=False):
+    """Measure the tuning on the current device (jq_autotune), as a dict;
+    circuit (named gates or a gates() tuple) is the tuning workload."""
+    t = Tuning()
+    flags = (JQ_TUNE_FORCE if force else 0) | (JQ_TUNE_NO_CACHE if no_cache else 0)
+    arr, cnt = (None, 0) if circuit is None else (circuit if isinstance(circuit, tuple) else gates(circuit))
+    check(lib().jq_autotune(n, ENCODINGS.get(enc, enc), flags, arr, cnt, ctypes.byref(t)))
+    return _tuning_dict(t)
 
 
 def plan_schedule(n, enc, circuit, fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0, search=JQ_SEARCH_AUTO):
