@@ -65,6 +65,10 @@ def parse():
                    help="comma-separated extras to run (per_target, c64, batch, serve, compact, compact_dense, "
                         "shor, aux, large), or all")
     p.add_argument("--cpu-gates", type=int, default=3, help="gates of the circuit the CPU oracle times")
+    p.add_argument("--metrics-log", metavar="PATH",
+                   help="append this run's records to a JSONL file: one line for the headline workload "
+                        "(config, seed, gates, fused passes, time, gates/s, GB/s, fraction of peak, counter "
+                        "bytes) and one per extra (errors, latencies, CPU timings with core counts)")
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the built-in tuning instead of measuring it on this device first")
     p.add_argument("--copy-calibration", type=int, default=4096, metavar="MIB",
@@ -339,7 +343,35 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, circuit, args.cpu_gates, batch_states=batch_states)
+    if args.metrics_log:
+        write_metrics_log(args.metrics_log, out)
     print(json.dumps(out))
+
+
+HEADLINE_KEYS = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "dtype", "data", "config",
+                 "norm", "hbm_gbps_step", "kernel_ms_per_step", "kernels", "roofline"]
+
+
+def write_metrics_log(path, out):
+    """Append one JSONL record for the headline workload and one per extra,
+    each tagged with a run id and the time."""
+    import datetime
+    import uuid
+
+    run = uuid.uuid4().hex[:12]
+    when = datetime.datetime.now(datetime.timezone.utc).isoformat(timespec="seconds")
+    head = {k: out[k] for k in HEADLINE_KEYS if k in out}
+    fused = out.get("kernels", {}).get("fused", {})
+    head.update({"run": run, "time": when, "workload": "headline",
+                 "fused_passes_per_step": fused.get("launches_per_step"),
+                 "frac_of_hbm_peak": out.get("roofline", {}).get("frac"),
+                 "counter_bytes_per_launch": out.get("roofline", {}).get("traffic")})
+    lines = [head] + [{"run": run, "time": when, "workload": k, "data": v}
+                      for k, v in out.items() if k not in HEADLINE_KEYS and k not in ("higher_is_better", "scaling",
+                                                                                       "vs_baseline")]
+    with open(path, "a") as f:
+        for rec in lines:
+            f.write(json.dumps(rec) + "\n")
 
 
 def compare_states(got, ref, n, chunk=1 << 24):

@@ -28,5 +28,24 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+# Host sanitizer build of both libraries (AddressSanitizer and
+# UndefinedBehaviorSanitizer, ROCm's clang so that one sanitizer runtime
+# serves them and the GPU library's sanitizer build in one process).
+CLANG = "/opt/rocm/llvm/bin/clang"
+SAN_DIR = os.path.join(os.path.dirname(HERE), "_build", "sanitize")
+SAN_LIB = os.path.join(SAN_DIR, "liboracle.so")
+SAN_PC_LIB = os.path.join(SAN_DIR, "libpapercpu.so")
+_SAN = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+        "-ffp-contract=off", "-std=c99", "-D_DEFAULT_SOURCE", "-shared", "-fPIC"]
+
+
+def build_sanitized() -> tuple:
+    os.makedirs(SAN_DIR, exist_ok=True)
+    subprocess.check_call([CLANG] + _SAN + ["-o", SAN_LIB, SRC, "-lm"])
+    subprocess.check_call([CLANG] + _SAN + ["-fopenmp", "-o", SAN_PC_LIB, PC_SRC, "-L/opt/rocm/llvm/lib",
+                                            "-Wl,-rpath,/opt/rocm/llvm/lib"])
+    return SAN_LIB, SAN_PC_LIB
+
+
 if __name__ == "__main__":
     print(build())

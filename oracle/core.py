@@ -23,9 +23,12 @@ _bp = ctypes.POINTER(ctypes.c_int8)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build(force=False)
-        L = ctypes.CDLL(LIB)
+        path = os.environ.get("JQ_ORACLE_LIB")  # another build (the sanitizer build, say)
+        if not path:
+            path = LIB
+            if not os.path.exists(LIB):
+                build(force=False)
+        L = ctypes.CDLL(path)
         L.oq_apply.argtypes = [_dp, ctypes.c_int, _ip, ctypes.c_int, _ip, ctypes.c_int, _dp]
         L.oq_run.argtypes = [_dp, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
         L.oq_norm2.argtypes = [_dp, ctypes.c_int]

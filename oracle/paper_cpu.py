@@ -19,9 +19,12 @@ _dp = ctypes.POINTER(ctypes.c_double)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(PC_LIB):
-            build(force=False)
-        L = ctypes.CDLL(PC_LIB)
+        path = os.environ.get("JQ_PAPERCPU_LIB")  # another build (the sanitizer build, say)
+        if not path:
+            path = PC_LIB
+            if not os.path.exists(PC_LIB):
+                build(force=False)
+        L = ctypes.CDLL(path)
         L.pc_run.argtypes = [_dp, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
         L.pc_run_many.argtypes = [ctypes.POINTER(_dp), ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int), ctypes.c_int,

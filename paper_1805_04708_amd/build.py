@@ -25,6 +25,8 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 # structurisation (which would otherwise merge the whole register tile
 # through chains of copy blocks)
 _UNIFORM = ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]
+# roctx ranges (JQ_ROCTX=1) come from the ROCm profiler SDK's marker library
+LIBS = ["-lpthread", "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 PER_FILE = {"kernels_compact.hip": ["-ffp-contract=off"] + _UNIFORM,
             "kernels_sv.hip": _UNIFORM, "batch.hip": _UNIFORM}
 
@@ -55,12 +57,60 @@ def build(verbose: bool = False) -> str:
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + LIBS
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     if verbose:
         print(LIB)
     return LIB
+
+
+# Host sanitizer build: the same library with AddressSanitizer and
+# UndefinedBehaviorSanitizer on the host code only (device code is built as
+# usual), for the CPU tests; load it with the sanitizer runtime preloaded
+# (see tests/test_sanitizers_cpu.py).
+SAN_DIR = os.path.join(BUILD, "sanitize")
+SAN_LIB = os.path.join(SAN_DIR, "libjq.so")
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
+def _compile_sanitized(src):
+    path = os.path.join(CSRC, src)
+    obj = os.path.join(SAN_DIR, src + ".o")
+    cmd = [HIPCC, "-O1", "-g", "-std=c++17", "-fPIC"] + PER_FILE.get(src, []) + SAN_HOST
+    if src.endswith(".hip"):
+        cmd += DEVICE + ["-x", "hip"]
+    cmd += ["-c", path, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-4000:]}")
+    return obj
+
+
+def build_sanitized() -> str:
+    os.makedirs(SAN_DIR, exist_ok=True)
+    srcs = _sources()
+    jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(_compile_sanitized, srcs))
+    tmp = SAN_LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + SAN_HOST + ["-Xarch_host", "-shared-libsan",
+                                                                              "-o", tmp] + objs + LIBS
+    subprocess.check_call(cmd)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
+def sanitizer_runtime() -> str:
+    """The AddressSanitizer runtime of the ROCm clang that built SAN_LIB."""
+    r = subprocess.run([HIPCC, "--print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        import glob
+        hits = glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so")
+        path = hits[0] if hits else ""
+    return path
 
 
 def ensure_built() -> str:

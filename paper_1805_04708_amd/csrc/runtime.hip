@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "internal.hpp"
 
 namespace jq {
@@ -106,6 +108,59 @@ void drain_profile(jq_state* s) {
     s->recs.clear();
 }
 
+// ------------------------------------------------------ debug switches --
+
+// Read once per process from the environment:
+//  JQ_LAUNCH_BLOCKING=1  wait for every kernel and check it before the call
+//                        returns (a device fault then names its step);
+//  JQ_FORCE_KERNEL=per_gate | fused
+//                        every circuit runs one kernel per gate, or every run
+//                        of fusable gates as a fused pass (results the same up
+//                        to rounding);
+//  JQ_ROCTX=1            roctx ranges around each call and each step, for
+//                        rocprofv3 --marker-trace.
+struct DebugFlags {
+    bool launch_blocking = false;
+    int force = 0;  // 0: none, 1: per gate, 2: fused
+    bool roctx = false;
+};
+
+const DebugFlags& debug_flags() {
+    static const DebugFlags f = [] {
+        DebugFlags d;
+        auto on = [](const char* v) { return v && v[0] && std::strcmp(v, "0") != 0; };
+        d.launch_blocking = on(std::getenv("JQ_LAUNCH_BLOCKING"));
+        d.roctx = on(std::getenv("JQ_ROCTX"));
+        if (const char* k = std::getenv("JQ_FORCE_KERNEL")) {
+            if (!std::strcmp(k, "per_gate")) d.force = 1;
+            else if (!std::strcmp(k, "fused")) d.force = 2;
+        }
+        return d;
+    }();
+    return f;
+}
+
+// A roctx range for the lifetime of the object (only with JQ_ROCTX set).
+struct Range {
+    bool on;
+    template <class F>
+    explicit Range(F&& label) : on(debug_flags().roctx) {
+        if (on) roctxRangePushA(label().c_str());
+    }
+    ~Range() {
+        if (on) roctxRangePop();
+    }
+};
+
+// With JQ_LAUNCH_BLOCKING: wait for the stream and report a failed step.
+void blocking_check(jq_state* s, const char* what) {
+    if (!debug_flags().launch_blocking) return;
+    const hipError_t e = hipStreamSynchronize(s->stream);
+    const hipError_t l = hipGetLastError();
+    if (e != hipSuccess || l != hipSuccess)
+        fail(JQ_EDEVICE, std::string(what) + ": " + hipGetErrorString(e != hipSuccess ? e : l));
+}
+
 // ---------------------------------------------------------- helpers --
 
 CompactBufs compact_bufs(jq_state* s) {
@@ -182,9 +237,16 @@ int kclass(const GateOp& op, int enc) {
 }
 
 void run_single(jq_state* s, const GateOp& op) {
-    Timed t(s, kclass(op, s->enc), op_bytes(op, s->n, s->enc));
-    if (s->enc == JQ_COMPACT) cp_apply_op(compact_bufs(s), s->n, op, s->stream);
-    else sv_apply_op(s->enc, s->buf, s->n, op, tuned_for(s->n, s->enc).wide_target, s->stream);
+    Range r([&] {
+        return std::string(kClassName[kclass(op, s->enc)]) + " t0=" + std::to_string(op.t0) +
+               " t1=" + std::to_string(op.t1);
+    });
+    {
+        Timed t(s, kclass(op, s->enc), op_bytes(op, s->n, s->enc));
+        if (s->enc == JQ_COMPACT) cp_apply_op(compact_bufs(s), s->n, op, s->stream);
+        else sv_apply_op(s->enc, s->buf, s->n, op, tuned_for(s->n, s->enc).wide_target, s->stream);
+    }
+    blocking_check(s, "per-gate kernel");
 }
 
 // Kernel layout per encoding: fixed lane bits F (128-byte lines for the
@@ -232,6 +294,8 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
         c.pass_ops = 150.0;
         if (!(opts && opts->fusion >= 2)) c.k_reg = 7;
     }
+    if (debug_flags().force == 1) c.fuse = false;
+    else if (debug_flags().force == 2) c.always_pass = true;
     while (c.fuse && c.k_reg > 2 && c.n < 6 + c.k_reg) c.k_reg--;
     return c;
 }
@@ -322,20 +386,35 @@ void run_step(jq_state* s, const std::vector<GateOp>& ops, const PlanConfig& cfg
     const double sweep = std::ldexp(1.0, s->n) * bytes_per_amp(s->enc);
     FPass p = step.pass;
     p.ops = dev_ops;
+    Range r([&] {
+        std::string q;
+        for (int j = 0; j < step.k_reg; ++j) q += (j ? "," : "") + std::to_string(p.reg_q[j]);
+        return "fused pass: " + std::to_string(p.n_ops) + " ops, " + std::to_string(step.n_gates) +
+               " gates, register qubits " + q;
+    });
     if (s->enc == JQ_COMPACT && cfg.code_domain) {
-        Timed t(s, K_CP_CODES, 2.0 * sweep);
-        cp_apply_codes(compact_bufs(s), s->n, p, step.k_reg, cfg.fixed_reg_bits, s->stream);
+        {
+            Timed t(s, K_CP_CODES, 2.0 * sweep);
+            cp_apply_codes(compact_bufs(s), s->n, p, step.k_reg, cfg.fixed_reg_bits, s->stream);
+        }
+        blocking_check(s, "two-byte code pass");
         return;
     }
     if (s->enc == JQ_COMPACT) {
         bool keeps = true;
         for (int g : step.gates) keeps = keeps && ops[g].keeps_modulus;
-        Timed t(s, K_CP_FUSED, (keeps ? 2.0 : 3.0) * sweep);
-        cp_apply_block(compact_bufs(s), s->n, p, step.k_reg, cfg.fixed_lane_bits, keeps, s->stream);
+        {
+            Timed t(s, K_CP_FUSED, (keeps ? 2.0 : 3.0) * sweep);
+            cp_apply_block(compact_bufs(s), s->n, p, step.k_reg, cfg.fixed_lane_bits, keeps, s->stream);
+        }
+        blocking_check(s, "two-byte fused block");
         return;
     }
-    Timed t(s, K_FUSED, 2.0 * sweep);
-    sv_apply_fused(s->enc, s->buf, s->n, p, step.k_reg, cfg.fixed_lane_bits, s->stream);
+    {
+        Timed t(s, K_FUSED, 2.0 * sweep);
+        sv_apply_fused(s->enc, s->buf, s->n, p, step.k_reg, cfg.fixed_lane_bits, s->stream);
+    }
+    blocking_check(s, "fused pass");
 }
 
 void apply_ops(jq_state* s, const std::vector<GateOp>& ops, const PlanConfig& cfg) {
@@ -740,6 +819,9 @@ int jq_apply_gate(jq_state* s, int kind, const int* qubits, int nq, const int* c
 int jq_apply_circuit(jq_state* s, const jq_gate* gates, size_t count, const jq_exec_opts* opts) {
     return guarded([&] {
         check_state(s);
+        Range r([&] {
+            return "jq_apply_circuit n=" + std::to_string(s->n) + " gates=" + std::to_string(count);
+        });
         const std::vector<GateOp> ops = lower_circuit(s, gates, count, "jq_apply_circuit");
         apply_ops(s, ops, plan_config(s->n, s->enc, opts));  // options validated before any work
     });

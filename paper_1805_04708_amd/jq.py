@@ -148,12 +148,15 @@ _lib = None
 
 
 def lib():
-    """Load libjq.so (raises if it has not been built: there is no fallback)."""
+    """Load libjq.so (raises if it has not been built: there is no fallback).
+    The environment variable JQ_LIB names another build of the library to
+    load instead (the host-sanitizer build, say)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            raise ImportError(f"{LIB} is missing: build it with `python -m paper_1805_04708_amd.build`")
-        L = ctypes.CDLL(LIB)
+        path = os.environ.get("JQ_LIB") or LIB
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with `python -m paper_1805_04708_amd.build`")
+        L = ctypes.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)
             f.restype = res

@@ -40,3 +40,20 @@ def test_compare_states_metrics():
     r = bench.compare_states(_FakeState(noisy), _FakeState(ref), n, chunk=1 << n)
     assert abs(r["fidelity"] - O.fidelity(noisy, ref)) < 1e-12
     assert abs(r["rel_l2"] - O.rel_l2(noisy, ref)) < 1e-12
+
+
+def test_metrics_log_records(tmp_path):
+    import json
+    out = {"metric": "m", "value": 1.5, "unit": "gates/s", "config": {"workload": "w", "seed": 3},
+           "kernels": {"fused": {"launches_per_step": 54.0}}, "roofline": {"frac": 0.5, "traffic": 7.0},
+           "higher_is_better": True, "c64_same_circuit": {"rel_l2_vs_c128": 1e-6},
+           "cpu_baseline": {"value": 0.3, "cores": 1}}
+    path = tmp_path / "m.jsonl"
+    bench.write_metrics_log(str(path), out)
+    bench.write_metrics_log(str(path), out)
+    recs = [json.loads(line) for line in path.read_text().splitlines()]
+    assert len(recs) == 6 and len({r["run"] for r in recs}) == 2
+    head = recs[0]
+    assert head["workload"] == "headline" and head["value"] == 1.5 and head["fused_passes_per_step"] == 54.0
+    assert head["config"]["seed"] == 3 and head["frac_of_hbm_peak"] == 0.5
+    assert {r["workload"] for r in recs[1:3]} == {"c64_same_circuit", "cpu_baseline"}

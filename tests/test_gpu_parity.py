@@ -551,3 +551,38 @@ def test_searched_plans_differ_and_match_the_oracle(enc, n):
     for search in (jq.JQ_SEARCH_ON, jq.JQ_SEARCH_OFF):
         got = run_gpu(n, enc, circ, init=psi, search=search)
         assert O.rel_l2(got, ref) <= tol(enc, len(circ)), (search, O.rel_l2(got, ref))
+
+
+GPU_SNIPPET = """
+import sys
+sys.path.insert(0, {root!r})
+import numpy as np
+import torch
+from oracle import core as O
+from paper_1805_04708_amd import jq, workloads as W
+torch.cuda.set_device(0)
+n = 14
+circ = W.layered_u2_cz(n, 3, seed=5) + W.random_circuit(n, 80, seed=6)
+ref = O.run(O.zero_state(n), n, circ)
+for enc, tol in (("c128", 1e-12), ("c64", 4e-6)):
+    with jq.State(n, enc) as s:
+        s.apply_circuit(circ)
+        err = O.rel_l2(s.amplitudes(), ref)
+        assert err <= tol, (enc, err)
+print("switches ok")
+"""
+
+
+@pytest.mark.parametrize("force", ["per_gate", "fused"])
+def test_debug_switches_keep_oracle_parity(force):
+    # a child process with every kernel waited for and checked
+    # (JQ_LAUNCH_BLOCKING), roctx ranges on, and the kernel class forced
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, JQ_LAUNCH_BLOCKING="1", JQ_ROCTX="1", JQ_FORCE_KERNEL=force)
+    print(f"child with JQ_FORCE_KERNEL={force}", flush=True)
+    r = subprocess.run([sys.executable, "-c", GPU_SNIPPET.format(root=root)], env=env, capture_output=True,
+                       text=True, timeout=240)
+    assert r.returncode == 0 and "switches ok" in r.stdout, r.stderr[-3000:]
