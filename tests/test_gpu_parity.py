@@ -227,6 +227,31 @@ def test_per_gate_kernel_variants_19_qubits(enc):
 
 
 @pytest.mark.parametrize("enc", ["c128", "c64"])
+def test_per_gate_access_orders_20_qubits(enc):
+    # one kernel per gate, controls on the index bits that change the
+    # kernels' access order: byte-address bits 10 and 20 (qubits 6 and 16
+    # for complex128, 7 and 17 for complex64: the chunks are dealt out in 64
+    # interleaved streams) and bits inside a 128-byte line (qubit 0 fixed:
+    # the whole state read and written; other low qubits: one thread per
+    # index), with selectors and phases on diagonals
+    n = 20
+    rng = np.random.default_rng(20)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    circ = []
+    for a, b in ((5, 6), (6, 7), (7, 8), (15, 16), (16, 17), (17, 18), (0, 1), (1, 2), (2, 3), (3, 4), (0, 19)):
+        circ += [("CZ", (a, b), ()), ("CP", (b, a), (float(rng.uniform(0, 6.28)),))]
+    circ += [("CNOT", (6, 10), ()), ("CNOT", (16, 3), ()), ("CNOT", (7, 1), ()), ("CNOT", (17, 19), ()),
+             ("MAT1", (4,), W.haar_u2(rng), (16,)), ("MAT1", (12,), W.haar_u2(rng), (7,)),
+             ("MAT1", (18,), W.haar_u2(rng), (6, 16)), ("TOFFOLI", (6, 16, 2), ()),
+             ("RZ", (5,), (0.3,), (0,)), ("RZ", (9,), (1.3,), (1, 3)), ("RZ", (0,), (2.1,), (6,)),
+             ("U", (2, 11), (3,), (0,)), ("T", (17,), (), (16,)), ("S", (3,), (), (2,))]
+    got = run_gpu(n, enc, circ, fusion=1, init=psi0)
+    ref = run_oracle(n, circ, init=psi0)
+    assert O.rel_l2(got, ref) <= tol(enc, len(circ)), O.rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
 @pytest.mark.parametrize("fusion", [1, 0])
 def test_random_circuit_16_qubits(enc, fusion):
     # the 16-qubit, 200-gate random circuit workload
