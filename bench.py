@@ -108,6 +108,30 @@ def traffic_from_profiles(kernel, workload):
 CPU_BATCH_SAMPLE = 512
 
 
+VALU_PEAK_PER_S = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions: 256 CUs x 4 SIMDs, 4 cycles each
+VALU_SOURCES = ["kernels_compact.hip", "fused_ops.hpp", "device_common.hpp", "internal.hpp", "planner.cpp"]
+
+
+def valu_roofline(kernel, workload, avg_ms):
+    """VALU-issue roofline of a VALU-bound kernel: its VALU instructions per
+    launch from the recorded rocprofv3 SQ_INSTS_VALU run (profiles/valu.json)
+    over the live launch time, against the issue peak; None if there is no
+    record or the sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "valu.json")
+    try:
+        rec = json.load(open(path)).get(f"{kernel}:{workload}")
+    except Exception:
+        return None
+    csrc = os.path.join(ROOT, "paper_1805_04708_amd", "csrc")
+    h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in VALU_SOURCES)).hexdigest()[:16]
+    if not rec or rec.get("source_hash") != h:
+        return None
+    achieved = rec["valu_insts_per_launch"] / (avg_ms * 1e-3)
+    return {"bound": "alu", "unit": "VALU instr/s", "achieved": achieved, "peak": VALU_PEAK_PER_S,
+            "frac": achieved / VALU_PEAK_PER_S, "valu_insts_per_launch": rec["valu_insts_per_launch"]}
+
+
 def cpu_baseline(n, circuit, gates, batch_states=None, batch_count=CPU_BATCH_SAMPLE, batch_seed=4096):
     """The CPU side, on this host's cores.
 
@@ -626,7 +650,10 @@ def compact_dense_extra(n=30, layers=2, seed=11):
         out[mode] = {"gates_per_s": len(circ) / dt, "seconds": dt, "blocks": len(blen), "fused_blocks": int(fused.sum()),
                      "fidelity_vs_c128": err["fidelity"], "rel_l2_vs_c128": err["rel_l2"],
                      "kernels": {k: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"],
-                                     "gbps": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in st.items()}}
+                                     "gbps": v["bytes"] / (v["ms"] * 1e-3) / 1e9,
+                                     "roofline": valu_roofline(k, f"n{n}_layered{layers}", v["ms"] / v["launches"])
+                                     if layers == 2 and seed == 11 else None}
+                                 for k, v in st.items()}}
     s.close()
     ref.close()
     return out
