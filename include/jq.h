@@ -134,6 +134,9 @@ typedef struct {
  *  wide_target: per-gate dense and X kernels take four amplitude pairs per
  *               thread for targets from this qubit up, one below it (0..64;
  *               64: never);
+ *  search:      the planner's large-state steps (see jq_exec_opts.search):
+ *               JQ_SEARCH_AUTO (on from 1 GiB of state up), JQ_SEARCH_ON or
+ *               JQ_SEARCH_OFF; an explicit opts->search wins;
  *  n_qubits:    the state size the values were tuned at (0: the built-in
  *               defaults);
  *  source:      JQ_TUNE_DEFAULT, JQ_TUNE_MEASURED (jq_autotune in this
@@ -160,6 +163,8 @@ typedef struct {
     int32_t source;
     double tuned_ms;
     double default_ms;
+    int32_t search;
+    int32_t reserved_;
 } jq_tuning;
 
 /* The tuning jq_apply_circuit uses for an N-qubit state of encoding enc on
@@ -180,7 +185,9 @@ int jq_tuning_set(int n_qubits, int enc, const jq_tuning *t);
  * 10 <= N <= 34) on the current device: a scratch state of 2^N amplitudes
  * runs a tuning circuit under each register width from 3 up and three
  * planner weights, and the fastest set is kept if it beats the defaults
- * (among those timed) by 2% or more; the per-gate threshold is the one
+ * (among those timed) by 2% or more; the large-state steps are then timed
+ * switched the other way than the size rule has them, and kept that way
+ * under the same 2% rule; the per-gate threshold is the one
  * that minimises the summed time of a dense gate on every target from 8 up,
  * kept under the same 2% rule.  The tuning circuit is gates[0..count-1]
  * (the caller's workload, validated as by jq_apply_circuit; the best

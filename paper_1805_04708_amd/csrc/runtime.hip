@@ -272,6 +272,8 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
     // the tile-slot search costs about 0.1 ms of host time per pass: worth
     // it once a pass streams 2 GiB or more
     c.search_rounds = std::ldexp((double)bytes_per_amp(enc), n) >= std::ldexp(1.0, 30) ? 2 : 0;
+    if (tune.search == JQ_SEARCH_ON) c.search_rounds = 2;
+    else if (tune.search == JQ_SEARCH_OFF) c.search_rounds = 0;
     // two-byte code, per-gate quantisation (the default): code-domain passes
     c.code_domain = compact;
     if (opts) {
@@ -304,6 +306,8 @@ PlanConfig plan_config_tuned(int n, int enc, int k_reg, double pass_ops) {
     PlanConfig c = plan_config(n, enc, nullptr);
     c.k_reg = k_reg;
     c.pass_ops = pass_ops;
+    // the size rule for the large-state steps, whatever is tuned now
+    c.search_rounds = std::ldexp((double)bytes_per_amp(enc), n) >= std::ldexp(1.0, 30) ? 2 : 0;
     while (c.fuse && c.k_reg > 2 && c.n < 6 + c.k_reg) c.k_reg--;
     return c;
 }

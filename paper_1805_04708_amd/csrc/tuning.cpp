@@ -170,6 +170,7 @@ bool parse_entry(Reader& r, Entry& e) {
             else if (key == "k_reg") e.t.k_reg = (int)v, have_k = v == std::floor(v);
             else if (key == "pass_ops") e.t.pass_ops = v, have_p = true;
             else if (key == "wide_target") e.t.wide_target = (int)v, have_w = v == std::floor(v);
+            else if (key == "search") e.t.search = (int)v;
             else if (key == "tuned_ms") e.t.tuned_ms = v;
             else if (key == "default_ms") e.t.default_ms = v;
         }
@@ -234,9 +235,10 @@ void write_cache_file(const std::string& path, const std::vector<Entry>& entries
             char buf[512];
             std::snprintf(buf, sizeof buf,
                           "%s\n  {\"device\": \"%s\", \"encoding\": \"%s\", \"n\": %d, \"k_reg\": %d, "
-                          "\"pass_ops\": %.17g, \"wide_target\": %d, \"tuned_ms\": %.17g, \"default_ms\": %.17g}",
+                          "\"pass_ops\": %.17g, \"wide_target\": %d, \"search\": %d, \"tuned_ms\": %.17g, "
+                          "\"default_ms\": %.17g}",
                           i ? "," : "", e.device.c_str(), enc_name(e.enc), e.n, e.t.k_reg, e.t.pass_ops,
-                          e.t.wide_target, e.t.tuned_ms, e.t.default_ms);
+                          e.t.wide_target, e.t.search, e.t.tuned_ms, e.t.default_ms);
             f << buf;
         }
         f << "\n]}\n";
@@ -262,6 +264,7 @@ bool valid(int enc, const jq_tuning& t) {
     if (t.k_reg < 2 || t.k_reg > k_max(enc)) return false;
     if (!(t.pass_ops > 0.0 && t.pass_ops <= 10000.0)) return false;
     if (t.wide_target < 0 || t.wide_target > 64) return false;
+    if (t.search != JQ_SEARCH_AUTO && t.search != JQ_SEARCH_ON && t.search != JQ_SEARCH_OFF) return false;
     return true;
 }
 
@@ -300,6 +303,7 @@ jq_tuning default_tuning(int enc) {
     t.k_reg = enc == JQ_C64 ? 5 : 4;
     t.pass_ops = enc == JQ_C64 ? 6.0 : 19.0;
     t.wide_target = 17;
+    t.search = JQ_SEARCH_AUTO;  // on from 1 GiB of state up (the planner's size rule)
     t.n_qubits = 0;
     t.source = JQ_TUNE_DEFAULT;
     return t;
@@ -448,6 +452,21 @@ jq_tuning measure(int n, int enc, const std::vector<GateOp>& workload) {
         best_ms = def_ms;
     }
     if (def_ms < 0) def_ms = best_ms;
+
+    // the large-state planner steps switched the other way than the size
+    // rule has them, for the chosen width and weight
+    {
+        PlanConfig cfg = plan_config_tuned(n, enc, best.k_reg, best.pass_ops);
+        const bool rule_on = cfg.search_rounds > 0;
+        cfg.search_rounds = rule_on ? 0 : 2;
+        state_apply_config(s, circ, cfg);  // warm
+        double t = 1e30;
+        for (int r = 0; r < 2; ++r) t = std::min(t, tm.ms(s->stream, [&] { state_apply_config(s, circ, cfg); }));
+        if (t < kMargin * best_ms) {
+            best.search = rule_on ? JQ_SEARCH_OFF : JQ_SEARCH_ON;
+            best_ms = t;
+        }
+    }
 
     // per-gate threshold: one dense gate on every target from 8 up with one
     // pair per thread and with four; the threshold minimising the sum

@@ -18,7 +18,7 @@ def _cache(tmp_path, monkeypatch):
     path = tmp_path / "tuning.json"
     monkeypatch.setenv("JQ_TUNE_CACHE", str(path))
     yield path
-    for n in (20, 26, 28, 30):
+    for n in (18, 20, 26, 28, 30):
         for enc in ("c128", "c64"):
             jq.tuning_set(n, enc, clear=True)
 
@@ -82,6 +82,26 @@ def test_overrides_win_and_are_validated(_cache):
     jq.tuning_set(28, "c64", k_reg=6)  # complex64 allows 6
     jq.tuning_set(28, "c128", clear=True)
     assert jq.tuning_get(28, "c128")["source"] == "cached"
+
+
+def test_tuned_search_switch(_cache):
+    # the large-state steps are off below 1 GiB by the size rule; a tuned
+    # value (from the cache file or set) turns them on, an explicit option wins
+    # (the cache file is read once per path: written before the first lookup)
+    n = 18
+    circ = W.layered_u2_cz(n, 6, seed=18)
+    write(_cache, [dict(entry(n, k=4, ops=19.0, wide=17), search=jq.JQ_SEARCH_ON)])
+    plain = jq.plan_steps(n, "c128", circ, search=jq.JQ_SEARCH_OFF)
+    searched = jq.plan_steps(n, "c128", circ, search=jq.JQ_SEARCH_ON)
+    assert plain != searched
+    assert jq.tuning_get(n, "c128")["search"] == jq.JQ_SEARCH_ON
+    assert jq.plan_steps(n, "c128", circ) == searched
+    assert jq.plan_steps(n, "c128", circ, search=jq.JQ_SEARCH_OFF) == plain
+    jq.tuning_set(n, "c128", search=jq.JQ_SEARCH_OFF)
+    assert jq.plan_steps(n, "c128", circ) == plain
+    with pytest.raises(jq.JqError):
+        jq.tuning_set(n, "c128", search=7)
+    jq.tuning_set(n, "c128", clear=True)
 
 
 def test_planner_uses_the_tuned_register_width():
