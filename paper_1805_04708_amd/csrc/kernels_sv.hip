@@ -38,8 +38,9 @@ __device__ __forceinline__ void st_pg(typename Vec<R>::T* p, uint64_t i, Cx<R> a
 // streams (chunk c takes slot (c mod 64) ilv + c / 64), so that the
 // requests in flight spread over the memory channels when a fixed control
 // bit sits on an address bit that selects them (measured: CZ(t, t+1) at
-// N=30 complex128 streams at 4.0-4.9 TB/s in order and 6.0-6.3 TB/s
-// interleaved for t = 5, 6, 15, 16, i.e. byte-address bits 10 and 20).
+// N=30 complex128 streams at 4.0-5.5 TB/s in order and 6.0-6.3 TB/s
+// interleaved for t = 5, 6, 7, 15, 16, i.e. byte-address bits 10, 11 and
+// 20; for other t the order is as fast or faster).
 __device__ __forceinline__ uint64_t chunk_slot(uint64_t c, uint64_t ilv) {
     return ilv ? (c & 63) * ilv + (c >> 6) : c;
 }
@@ -375,13 +376,13 @@ bool partial_lines(uint64_t cmask) {
 }
 
 // The chunk interleave for a per-gate kernel (see chunk_slot): on when a
-// fixed control bit of the op lies on byte-address bit 10 or 20 (the bits
-// measured to concentrate in-order requests on few channels) and the
+// fixed control bit of the op lies on byte-address bit 10, 11 or 20 (the
+// bits measured to concentrate in-order requests on few channels) and the
 // chunks are full and a multiple of 64.
 template <typename R>
 uint64_t chunk_interleave(uint64_t ngroups, uint64_t per_chunk, uint64_t cmask) {
     constexpr int lb = sizeof(R) == 8 ? 4 : 3;  // log2 of the amplitude's bytes
-    const uint64_t channel_bits = (1ull << (10 - lb)) | (1ull << (20 - lb));
+    const uint64_t channel_bits = (1ull << (10 - lb)) | (1ull << (11 - lb)) | (1ull << (20 - lb));
     if (!(cmask & channel_bits) || ngroups % per_chunk) return 0;
     const uint64_t nchunks = ngroups / per_chunk;
     return nchunks >= 64 && nchunks % 64 == 0 ? nchunks / 64 : 0;

@@ -239,7 +239,7 @@ def test_per_gate_access_orders_20_qubits(enc):
     psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
     psi0 /= np.linalg.norm(psi0)
     circ = []
-    for a, b in ((5, 6), (6, 7), (7, 8), (15, 16), (16, 17), (17, 18), (0, 1), (1, 2), (2, 3), (3, 4), (0, 19)):
+    for a, b in ((5, 6), (6, 7), (7, 8), (15, 16), (16, 17), (17, 18), (0, 1), (1, 2), (2, 3), (3, 4), (0, 19), (8, 9)):
         circ += [("CZ", (a, b), ()), ("CP", (b, a), (float(rng.uniform(0, 6.28)),))]
     circ += [("CNOT", (6, 10), ()), ("CNOT", (16, 3), ()), ("CNOT", (7, 1), ()), ("CNOT", (17, 19), ()),
              ("MAT1", (4,), W.haar_u2(rng), (16,)), ("MAT1", (12,), W.haar_u2(rng), (7,)),
