@@ -151,11 +151,21 @@ __global__ __launch_bounds__(kBlock) void k_probs(L ldr, InsN others, Dep sel, u
     const uint64_t hi = lo + chunk < n_w ? lo + chunk : n_w;
     uint64_t binoff = 0;
     for (int m = 0; m < sel.nq; ++m) binoff |= ((bin >> m) & 1ull) << sel.q[m];
+    auto term = [&](uint64_t o) {
+        if constexpr (W == 1) return ldr.modulus2(expand_n(o, others) | binoff);
+        else return ldr.template modulus2_w<W>(expand_n(o * W, others) | binoff);
+    };
+    // eight loads in flight per thread; the sum still runs in index order
     double acc = 0.0;
-    for (uint64_t o = lo + threadIdx.x; o < hi; o += kBlock) {
-        if constexpr (W == 1) acc += ldr.modulus2(expand_n(o, others) | binoff);
-        else acc += ldr.template modulus2_w<W>(expand_n(o * W, others) | binoff);
+    uint64_t o = lo + threadIdx.x;
+    for (; o + 7 * kBlock < hi; o += 8 * kBlock) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = term(o + u * kBlock);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += t[u];
     }
+    for (; o < hi; o += kBlock) acc += term(o);
     const double s = block_sum(acc, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
@@ -189,14 +199,29 @@ __global__ __launch_bounds__(kBlock) void k_expect(L ldr, Ins ins, uint64_t qbit
     const uint64_t lo = (uint64_t)blockIdx.x * chunk;
     const uint64_t hi = lo + chunk < npairs ? lo + chunk : npairs;
     double sx = 0, sy = 0, sz = 0, nr = 0;
-    for (uint64_t g = lo + threadIdx.x; g < hi; g += kBlock) {
-        const uint64_t i = expand(g, ins);
-        const Cx<double> a = ldr.amp(i), b = ldr.amp(i | qbit);
+    auto add = [&](const Cx<double>& a, const Cx<double>& b) {
         sx += 2.0 * (a.re * b.re + a.im * b.im);
         sy += 2.0 * (a.re * b.im - a.im * b.re);
         const double pa = a.re * a.re + a.im * a.im, pb = b.re * b.re + b.im * b.im;
         sz += pa - pb;
         nr += pa + pb;
+    };
+    // four pairs (eight loads) in flight per thread, summed in index order
+    uint64_t g = lo + threadIdx.x;
+    for (; g + 3 * kBlock < hi; g += 4 * kBlock) {
+        Cx<double> a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t i = expand(g + u * kBlock, ins);
+            a[u] = ldr.amp(i);
+            b[u] = ldr.amp(i | qbit);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add(a[u], b[u]);
+    }
+    for (; g < hi; g += kBlock) {
+        const uint64_t i = expand(g, ins);
+        add(ldr.amp(i), ldr.amp(i | qbit));
     }
     double r[4] = {sx, sy, sz, nr};
     for (int c = 0; c < 4; ++c) {
@@ -346,14 +371,24 @@ void launch_probs(const L& ldr, int n, const int* qubits, int nq, double* out, d
         JQ_HIP(hipGetLastError());
         return;
     }
+    bool wide = W > 1 && n_others >= (uint64_t)W * kBlock;
+    for (int m = 0; m < nq && wide; ++m) wide = (1ull << qubits[m]) >= (uint64_t)W;
+    // Blocks: one resident round of the device for up to 64 bins (each block
+    // streams one long chunk), two rounds for more bins, whose zero-bit
+    // insertion costs more arithmetic per amplitude (both measured).
+    int dev = 0, cus = 0, per_cu = 0;
+    JQ_HIP(hipGetDevice(&dev));
+    JQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    JQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, wide ? (const void*)k_probs<L, W> : (const void*)k_probs<L, 1>, kBlock, 0));
+    const uint64_t round = (uint64_t)(cus > 0 ? cus : 1) * (uint64_t)(per_cu > 0 ? per_cu : 1);
     uint64_t parts = n_others / (kBlock * 16);
     if (parts < 1) parts = 1;
-    const uint64_t want = 4096 / nbins + 1;
+    uint64_t want = (nbins <= 64 ? round : 2 * round) / nbins;
+    if (want < 1) want = 1;
     if (parts > want) parts = want;
     if (nbins * parts > cap) parts = cap / nbins;
     if (parts < 1) fail(JQ_EINVAL, "reduction scratch too small");
-    bool wide = W > 1 && n_others >= (uint64_t)W * kBlock;
-    for (int m = 0; m < nq && wide; ++m) wide = (1ull << qubits[m]) >= (uint64_t)W;
     if (wide) {
         if constexpr (W > 1)
             hipLaunchKernelGGL((k_probs<L, W>), dim3((unsigned)(nbins * parts)), dim3(kBlock), 0, st, ldr, others, d,
