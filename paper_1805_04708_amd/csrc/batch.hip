@@ -270,7 +270,10 @@ __device__ void run_block(typename Vec<R>::T* S, int n, const BBlock& blk, const
 // pass makes its stores visible to the next pass's loads (one workgroup, one
 // compute unit).  In batch plans a pass's ops field holds the index of its
 // first op in fops (a kernel argument, so the ops are read with scalar
-// loads).
+// loads).  The state starts as |0...0>, which the first pass does not read:
+// tile 0 (the one holding index 0, in lane 0, slot 0) starts from its
+// values, and every other tile is zero before the pass and so after it
+// (every op is linear), so it is only written.
 template <typename R>
 __device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* __restrict__ passes, int n_passes,
                           const FOp* __restrict__ fops) {
@@ -292,13 +295,29 @@ __device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* __restric
         for (uint64_t t = wave; t < ntiles; t += nw) {
             uint64_t base = tile_base(P, t, lane_off);
             Cx<R> a[S];
+            if (p == 0) {
+                if (t != 0) {
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                uint64_t off = 0;
+                    for (int s = 0; s < S; ++s) {
+                        uint64_t off = 0;
 #pragma unroll
-                for (int j = 0; j < K; ++j)
-                    if (s & (1 << j)) off += stride[j];
-                a[s] = ld<R>(psi, base + off);
+                        for (int j = 0; j < K; ++j)
+                            if (s & (1 << j)) off += stride[j];
+                        st<R>(psi, base + off, Cx<R>{(R)0, (R)0});
+                    }
+                    continue;
+                }
+#pragma unroll
+                for (int s = 0; s < S; ++s) a[s] = Cx<R>{(R)(s == 0 && lane == 0 ? 1 : 0), (R)0};
+            } else {
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    uint64_t off = 0;
+#pragma unroll
+                    for (int j = 0; j < K; ++j)
+                        if (s & (1 << j)) off += stride[j];
+                    a[s] = ld<R>(psi, base + off);
+                }
             }
             run_ops<R, K>(a, ops, n_ops, base, wave_uniform(tile_base(P, t, 0)), lane);
             // recompute the store addresses instead of keeping 2^K of them live
@@ -379,13 +398,17 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_tiles(typename Vec<R>::
         const BCirc c = circs[order[w]];
         const uint32_t dim = 1u << c.n;
         typename Vec<R>::T* S = arena + c.state_off;
-        for (uint32_t i = threadIdx.x; i < dim; i += blockDim.x) {
-            typename Vec<R>::T v;
-            v.x = (R)(i == 0 ? 1 : 0);
-            v.y = (R)0;
-            S[i] = v;
+        if (c.n_passes == 0) {
+            // no gates: the state is |0...0>
+            for (uint32_t i = threadIdx.x; i < dim; i += blockDim.x) {
+                typename Vec<R>::T v;
+                v.x = (R)(i == 0 ? 1 : 0);
+                v.y = (R)0;
+                S[i] = v;
+            }
+            __syncthreads();
+            continue;
         }
-        __syncthreads();
         run_tiles<R>(S, c.n, passes + c.first_pass, c.n_passes, fops);
     }
 }
