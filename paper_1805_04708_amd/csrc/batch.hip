@@ -270,10 +270,18 @@ __device__ void run_block(typename Vec<R>::T* S, int n, const BBlock& blk, const
 // pass makes its stores visible to the next pass's loads (one workgroup, one
 // compute unit).  In batch plans a pass's ops field holds the index of its
 // first op in fops (a kernel argument, so the ops are read with scalar
-// loads).  The state starts as |0...0>, which the first pass does not read:
-// tile 0 (the one holding index 0, in lane 0, slot 0) starts from its
-// values, and every other tile is zero before the pass and so after it
-// (every op is linear), so it is only written.
+// loads).
+//
+// The state starts as |0...0>, and a pass moves amplitude only along its
+// tile's qubits (every op is linear, and its selectors and controls outside
+// the tile only choose among matrices): after passes 0..p-1 the state is
+// zero at every index with a bit set outside the union of their tile
+// qubits (the support).  So the first pass reads nothing: tile 0 (holding
+// index 0, in lane 0, slot 0) starts from its values, and every other tile
+// is zero before the pass and so after it, and is only written.  A later
+// pass skips every tile with an outer bit set outside the support: zero
+// before and after, and still zero in memory since the first pass wrote it.
+// The other (active) tiles are enumerated directly, spread over the waves.
 template <typename R>
 __device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* __restrict__ passes, int n_passes,
                           const FOp* __restrict__ fops) {
@@ -282,6 +290,7 @@ __device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* __restric
     const uint64_t wave = (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t nw = blockDim.x >> 6;
     const uint64_t ntiles = 1ull << (n - 6 - K);
+    uint64_t support = 0;  // qubits of the tiles of the passes so far
     for (int p = 0; p < n_passes; ++p) {
         const FPass& P = passes[p];
         uint64_t lane_off = (uint64_t)(lane & ((1 << F) - 1));
@@ -292,7 +301,27 @@ __device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* __restric
         for (int j = 0; j < K; ++j) stride[j] = 1ull << P.reg_q[j];
         const FOp* ops = fops + reinterpret_cast<uintptr_t>(P.ops);
         const int n_ops = P.n_ops;
-        for (uint64_t t = wave; t < ntiles; t += nw) {
+        uint64_t tmask = 0;
+        for (int i = 0; i < P.n_tile; ++i) tmask |= 1ull << P.tile_sorted[i];
+        // bit k of a tile number is the k-th lowest qubit outside the tile;
+        // act: the bits whose qubit is in the support
+        uint64_t act = 0;
+        for (int q = 0, k = 0; q < n; ++q) {
+            if ((tmask >> q) & 1) continue;
+            if ((support >> q) & 1) act |= 1ull << k;
+            ++k;
+        }
+        const uint64_t n_visit = p == 0 ? ntiles : 1ull << __builtin_popcountll(act);
+        for (uint64_t j = wave; j < n_visit; j += nw) {
+            // the first pass visits every tile; a later one the j-th active
+            // tile (j's bits deposited at the set bits of act)
+            uint64_t t = j;
+            if (p > 0) {
+                t = 0;
+                uint64_t jj = j;
+                for (uint64_t m = act; m; m &= m - 1, jj >>= 1)
+                    if (jj & 1) t |= m & (~m + 1);
+            }
             uint64_t base = tile_base(P, t, lane_off);
             Cx<R> a[S];
             if (p == 0) {
@@ -331,6 +360,7 @@ __device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* __restric
                 st<R>(psi, base + off, a[s]);
             }
         }
+        support |= tmask;
         __syncthreads();
     }
 }

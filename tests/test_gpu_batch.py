@@ -120,6 +120,58 @@ def test_batch_tile_mode_large_states(enc, tol):
     b.close()
 
 
+def support_growth_circuits(n, rng):
+    """Circuits whose passes widen the set of qubits the state may occupy a
+    few at a time, with controls, selectors and diagonals on qubits outside
+    it (tile mode then visits only part of the later passes' tiles)."""
+    low = list(range(10))
+    high = list(range(10, n))
+    a = [("H", (q,), ()) for q in low]
+    # controls and a phase selector on qubits the state does not occupy yet
+    a += [("MAT1", (3,), W.haar_u2(rng), (high[-1],)), ("CP", (high[0], 5), (0.7,)), ("RZ", (high[1],), (1.1,))]
+    # spread to one high qubit at a time, with dense gates in between
+    for k, h in enumerate(high):
+        a.append(("CNOT", (low[k % 10], h), ()))
+        a.append(("MAT1", (low[(3 * k) % 10],), W.haar_u2(rng)))
+        if k % 2:
+            a.append(("CP", (h, high[(k + 1) % len(high)]), (0.3 + k,)))
+    a += [("MAT1", (h,), W.haar_u2(rng)) for h in high[::2]]
+    a += mixed_circuit(n, 30, rng)
+    # only the low qubits: one pass, the rest of the state stays exactly zero
+    b = [("H", (q,), ()) for q in low] + [("CNOT", (0, 9), ()), ("T", (4,), ())]
+    # only diagonals outside the first pass's qubits
+    c = [("H", (0,), ()), ("RZ", (high[0],), (0.4,)), ("CP", (high[-1], high[0]), (1.3,)), ("Z", (high[1],), ())]
+    return [a, b, c, []]
+
+
+@pytest.mark.parametrize("enc,tol", [("c128", 1e-12), ("c64", 5e-6)])
+def test_batch_tile_mode_support_growth(enc, tol):
+    # tile mode skips, in every pass after the first, the tiles with an
+    # index bit set outside the qubits of the passes so far (zero before
+    # and after the pass): states against the oracle, alone against in the
+    # batch bit for bit, and exact zeros outside a one-pass circuit's qubits
+    rng = np.random.default_rng(1805)
+    inst = []
+    for n in (13, 14, 16):
+        inst += [(n, c) for c in support_growth_circuits(n, rng)]
+    b = jq.Batch(inst, enc, fusion=4)
+    b.run()
+    for i, (n, circ) in enumerate(inst):
+        got = b.amplitudes(i)
+        ref = oracle_state(n, circ)
+        assert O.rel_l2(got, ref) <= tol, (i, n, O.rel_l2(got, ref))
+        alone = jq.Batch([inst[i]], enc, fusion=4)
+        alone.run()
+        assert np.array_equal(alone.amplitudes(0), got), i
+        alone.close()
+        if i % 4 == 1:
+            outside = np.arange(1 << n) >= (1 << 10)
+            assert not np.any(got[outside]), i
+        if not circ:
+            assert got[0] == 1 and not np.any(got[1:]), i
+    b.close()
+
+
 def test_batch_rejects_bad_input():
     with pytest.raises(jq.JqError):
         jq.Batch([(21, [])], "c128")
