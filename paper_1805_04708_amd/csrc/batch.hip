@@ -21,7 +21,9 @@
 // circuits run in their own kernel, without LDS, on a second stream forked
 // from the batch's stream, concurrently with the block-mode kernel.
 //
-// The depth is tuned per (encoding, N) on first use in the process.
+// The depth is tuned per (encoding, N) on first use in the process, then the
+// launch policy (which kernel starts first, and the block kernel's LDS
+// request) per encoding.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -546,6 +548,10 @@ void plan_blocks(const std::vector<GateOp>& ops, int n, int kb, std::vector<BBlo
 
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, int> g_tuned_kb;  // (enc, n) -> kb
+std::map<int, int> g_tuned_policy;              // enc -> launch policy
+
+constexpr int kPolicyBlockFirst = 1;
+constexpr int kPolicyFitLds = 2;
 
 }  // namespace
 
@@ -573,7 +579,12 @@ struct jq_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int lds_max_n = 0;
-    size_t lds_bytes = 0;
+    size_t lds_bytes = 0;      // the block kernel's LDS when the policy does not size it
+    size_t lds_fit_bytes = 0;  // the largest LDS-resident block-mode state
+    int per_cu_blk_fit = 1;    // occupancy of the block kernel with lds_fit_bytes
+    // launch policy (tuned): kPolicyBlockFirst launches the block kernel
+    // before the tile kernel; kPolicyFitLds gives it only lds_fit_bytes
+    int policy = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<std::vector<jq::GateOp>> ops_host;
     std::vector<int> kb;  // fusion depth used per circuit
@@ -680,6 +691,15 @@ void upload_plans(jq_batch* b) {
     std::stable_sort(ot.begin(), ot.end(), larger);
     b->count_blk = (uint32_t)ob.size();
     b->count_tile = (uint32_t)ot.size();
+    {
+        int mx = 0;
+        for (int32_t i : ob) mx = std::max(mx, std::min(b->n[i], b->lds_max_n));
+        b->lds_fit_bytes = (size_t)bytes_per_amp(b->enc) << mx;
+        const void* kfn = b->enc == JQ_C128 ? (const void*)k_batch<double> : (const void*)k_batch<float>;
+        JQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->per_cu_blk_fit, kfn, kBatchThreads,
+                                                            b->lds_fit_bytes));
+        b->per_cu_blk_fit = std::max(1, b->per_cu_blk_fit);
+    }
     if (ob.empty()) ob.push_back(0);
     if (ot.empty()) ot.push_back(0);
     for (void* p : {b->circs, b->blocks, b->ops, b->passes, b->fops, b->order, b->order_tile})
@@ -701,12 +721,14 @@ void upload_plans(jq_batch* b) {
     JQ_HIP(hipMemcpy(b->passes, passes.data(), passes.size() * sizeof(FPass), hipMemcpyHostToDevice));
 }
 
+// The two kernels are persistent and run concurrently, each pulling its own
+// work list; the one launched first takes the compute units first, and the
+// block kernel's LDS request bounds how many of its workgroups share a unit
+// with the tile kernel's (both choices are tuned: see autotune).
 void launch(jq_batch* b) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, b->counter);
     JQ_HIP(hipGetLastError());
-    if (b->count_tile) {
-        // tile kernel on the second stream, concurrent with the block kernel
-        JQ_HIP(hipEventRecord(b->ev_fork, b->stream));
+    auto launch_tiles = [&] {
         JQ_HIP(hipStreamWaitEvent(b->stream2, b->ev_fork, 0));
         const unsigned grid = (unsigned)std::max(1, std::min<int>((int)b->count_tile, b->cus * b->per_cu_tile));
         if (b->enc == JQ_C128)
@@ -719,21 +741,30 @@ void launch(jq_batch* b) {
                                b->count_tile, (const FPass*)b->passes, (const FOp*)b->fops, b->counter + 1);
         JQ_HIP(hipGetLastError());
         JQ_HIP(hipEventRecord(b->ev_join, b->stream2));
-    }
+    };
+    // the tile kernel's stream forks from here, before the block kernel, so
+    // that neither kernel waits for the other
+    if (b->count_tile) JQ_HIP(hipEventRecord(b->ev_fork, b->stream));
+    const bool block_first = (b->policy & kPolicyBlockFirst) != 0;
+    if (b->count_tile && !block_first) launch_tiles();
     if (b->count_blk) {
-        const unsigned grid = (unsigned)std::max(1, std::min<int>((int)b->count_blk, b->cus * b->per_cu_blk));
+        const bool fit = (b->policy & kPolicyFitLds) != 0;
+        const size_t lds = fit ? b->lds_fit_bytes : b->lds_bytes;
+        const int per_cu = fit ? b->per_cu_blk_fit : b->per_cu_blk;
+        const unsigned grid = (unsigned)std::max(1, std::min<int>((int)b->count_blk, b->cus * per_cu));
         if (b->enc == JQ_C128)
-            hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBatchThreads), b->lds_bytes, b->stream,
+            hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBatchThreads), lds, b->stream,
                                (double2*)b->arena, (const BCirc*)b->circs, (const int32_t*)b->order,
                                b->count_blk, (const BBlock*)b->blocks, (const BOp*)b->ops, b->counter,
                                b->lds_max_n);
         else
-            hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBatchThreads), b->lds_bytes, b->stream,
+            hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBatchThreads), lds, b->stream,
                                (float2*)b->arena, (const BCirc*)b->circs, (const int32_t*)b->order,
                                b->count_blk, (const BBlock*)b->blocks, (const BOp*)b->ops, b->counter,
                                b->lds_max_n);
         JQ_HIP(hipGetLastError());
     }
+    if (b->count_tile && block_first) launch_tiles();
     if (b->count_tile) JQ_HIP(hipStreamWaitEvent(b->stream, b->ev_join, 0));
 }
 
@@ -756,18 +787,53 @@ float trial_ms(jq_batch* b) {
     return best;
 }
 
+void tune_depths(jq_batch* b);
+
+// The launch policy per encoding: on first use in the process, each of the
+// four (block kernel first or not, its LDS sized to its states or not) is
+// timed on the batch with its tuned depths, and the fastest kept.
+void tune_policy(jq_batch* b) {
+    auto it = g_tuned_policy.find(b->enc);
+    if (it != g_tuned_policy.end()) {
+        b->policy = it->second;
+        return;
+    }
+    upload_plans(b);
+    float best_ms = 0;
+    int best = 0;
+    for (int pol = 0; pol < 4; ++pol) {
+        b->policy = pol;
+        const float ms = trial_ms(b);
+        if (pol == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = pol;
+        }
+    }
+    b->policy = best;
+    g_tuned_policy[b->enc] = best;
+}
+
+void autotune(jq_batch* b, const jq_exec_opts* opts) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (opts && opts->fusion >= 1) {
+        // depth 4 and up: tile mode where it applies (blocks of 3 elsewhere);
+        // the launch policy as tuned in this process, if it was
+        for (size_t i = 0; i < b->count; ++i)
+            b->kb[i] = opts->fusion >= kTileDepth ? kTileDepth : std::min(opts->fusion, std::min(3, b->n[i]));
+        auto it = g_tuned_policy.find(b->enc);
+        b->policy = it != g_tuned_policy.end() ? it->second : 0;
+        return;
+    }
+    tune_depths(b);
+    tune_policy(b);
+}
+
 // Fusion depth per (encoding, N): the first batch that meets an untuned N
 // times every depth on its circuits of that N (all depths give the same
 // state up to rounding) and keeps the fastest for the rest of the process,
-// so a circuit runs the same code in every batch of this process.
-void autotune(jq_batch* b, const jq_exec_opts* opts) {
-    if (opts && opts->fusion >= 1) {
-        // depth 4 and up: tile mode where it applies (blocks of 3 elsewhere)
-        for (size_t i = 0; i < b->count; ++i)
-            b->kb[i] = opts->fusion >= kTileDepth ? kTileDepth : std::min(opts->fusion, std::min(3, b->n[i]));
-        return;
-    }
-    std::lock_guard<std::mutex> lk(g_tune_mu);
+// so a circuit runs the same code in every batch of this process.  The
+// caller holds g_tune_mu.
+void tune_depths(jq_batch* b) {
     std::map<int, std::vector<size_t>> by_n;
     for (size_t i = 0; i < b->count; ++i) by_n[b->n[i]].push_back(i);
     std::vector<int> untuned;
