@@ -186,6 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_probs_by_bin(L ldr, InsN others, Dep
 
 __global__ void k_sum_parts(const double* __restrict__ partial, uint64_t nbins, uint32_t parts,
                             double* __restrict__ out);
+__global__ void k_sum_parts_wave(const double* __restrict__ partial, uint32_t parts, double* __restrict__ out);
 
 // Sums over amplitude pairs (i, j = i | 2^q) of 2 Re(conj(a_i) a_j),
 // 2 Im(conj(a_i) a_j), |a_i|^2 - |a_j|^2 and |a_i|^2 + |a_j|^2: the
@@ -398,8 +399,13 @@ void launch_probs(const L& ldr, int n, const int* qubits, int nq, double* out, d
                            n_others, (uint32_t)parts, partial);
     }
     JQ_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(nbins, 64)), dim3(64), 0, st, partial, nbins, (uint32_t)parts,
-                       out);
+    // the parts of a bin in a fixed order: by one thread when they are few,
+    // by one wave per bin otherwise (64 times shorter a chain of loads)
+    if (parts < 64)
+        hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(nbins, 64)), dim3(64), 0, st, partial, nbins,
+                           (uint32_t)parts, out);
+    else
+        hipLaunchKernelGGL(k_sum_parts_wave, dim3((unsigned)nbins), dim3(64), 0, st, partial, (uint32_t)parts, out);
     JQ_HIP(hipGetLastError());
 }
 

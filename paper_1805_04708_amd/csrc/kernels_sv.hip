@@ -337,15 +337,28 @@ __global__ void k_sum_parts(const double* __restrict__ partial, uint64_t nbins, 
     out[b] = s;
 }
 
+// The sum of n values in a fixed order by one wave: lane l adds values l,
+// l + 64, ... in turn, then the lanes combine by halving distance.  Every
+// lane must call it; lane 0 gets the sum.
+__device__ __forceinline__ double wave_sum_fixed(const double* __restrict__ v, uint32_t n) {
+    double s = 0.0;
+    for (uint32_t p = threadIdx.x & 63; p < n; p += 64) s += v[p];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    return s;
+}
+
+// Many parts per bin: one 64-thread block (a wave) per bin.
+__global__ void k_sum_parts_wave(const double* __restrict__ partial, uint32_t parts, double* __restrict__ out) {
+    const double s = wave_sum_fixed(partial + (uint64_t)blockIdx.x * parts, parts);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// One 64-thread block.
 __global__ void k_expect_final(const double* __restrict__ partial, uint32_t parts, int q, int n,
                                double* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double s[4];
-    for (int c = 0; c < 4; ++c) {
-        double t = 0.0;
-        for (uint32_t p = 0; p < parts; ++p) t += partial[(uint64_t)c * parts + p];
-        s[c] = t;
-    }
+    for (int c = 0; c < 4; ++c) s[c] = wave_sum_fixed(partial + (uint64_t)c * parts, parts);
+    if (threadIdx.x != 0) return;
     out[q] = (1.0 - s[0] / s[3]) / 2.0;
     out[n + q] = (1.0 - s[1] / s[3]) / 2.0;
     out[2 * n + q] = (1.0 - s[2] / s[3]) / 2.0;
