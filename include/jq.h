@@ -261,6 +261,19 @@ int jq_set_allocator(void *(*alloc)(size_t, void *), void (*release)(void *, voi
  * (nq = 0) that jq_apply_circuit skips. */
 int jq_gate_named(const char *name, const int *qubits, int nq, const double *params, int np, jq_gate *out);
 
+/* Lower count named instructions in one call: jq_gate_named on each, then
+ * instruction i's extra controls appended to its record (after the
+ * controls its name implies).  names[i] is instruction i's name; nq[i],
+ * np[i] and nc[i] count its qubits, parameters and extra controls, whose
+ * values follow one another, instruction by instruction, in qubits, params
+ * and controls (each may be NULL when its counts are all zero; nc itself
+ * may be NULL: no extra controls).  out holds count records.  Host only.
+ * Returns JQ_OK, or JQ_EINVAL for the first bad instruction (its index in
+ * jq_last_error; the records before it are filled) or for more than
+ * JQ_MAX_CONTROLS controls in one record. */
+int jq_gates_named(size_t count, const char *const *names, const int *nq, const int *qubits, const int *np,
+                   const double *params, const int *nc, const int *controls, jq_gate *out);
+
 /* Apply one gate (Sec. 2, Eq. NUM2 and its four-amplitude analogue).
  * matrix is copied before return.  JQ_EINVAL if the qubits are invalid or
  * the matrix does not fit the kind (e.g. a non-zero off-diagonal entry for

@@ -798,6 +798,32 @@ int jq_gate_named(const char* name, const int* qubits, int nq, const double* par
     return guarded([&] { gate_named(name, qubits, nq, params, np, out); });
 }
 
+int jq_gates_named(size_t count, const char* const* names, const int* nq, const int* qubits, const int* np,
+                   const double* params, const int* nc, const int* controls, jq_gate* out) {
+    return guarded([&] {
+        if (count > 0 && (!names || !nq || !np || !out)) fail(JQ_EINVAL, "jq_gates_named: null argument");
+        size_t qo = 0, po = 0, co = 0;
+        for (size_t i = 0; i < count; ++i) {
+            const std::string at = "jq_gates_named: instruction " + std::to_string(i) + ": ";
+            const int k = nc ? nc[i] : 0;
+            if (nq[i] < 0 || np[i] < 0 || k < 0) fail(JQ_EINVAL, at + "negative count");
+            if ((nq[i] > 0 && !qubits) || (np[i] > 0 && !params) || (k > 0 && !controls))
+                fail(JQ_EINVAL, at + "null argument");
+            try {
+                gate_named(names[i], nq[i] ? qubits + qo : nullptr, nq[i], np[i] ? params + po : nullptr, np[i],
+                           &out[i]);
+            } catch (const Error& e) {
+                fail(e.code, at + e.what());
+            }
+            if (out[i].nc + k > JQ_MAX_CONTROLS) fail(JQ_EINVAL, at + "too many controls");
+            for (int c = 0; c < k; ++c) out[i].controls[out[i].nc++] = controls[co + c];
+            qo += (size_t)nq[i];
+            po += (size_t)np[i];
+            co += (size_t)k;
+        }
+    });
+}
+
 int jq_apply_gate(jq_state* s, int kind, const int* qubits, int nq, const int* controls, int nc,
                   const double* matrix) {
     return guarded([&] {

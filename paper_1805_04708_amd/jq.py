@@ -97,6 +97,8 @@ SIGNATURES = {
     "jq_synchronize": (ctypes.c_int, [_VP]),
     "jq_set_allocator": (ctypes.c_int, [_VP, _VP, _VP]),
     "jq_gate_named": (ctypes.c_int, [ctypes.c_char_p, _IP, ctypes.c_int, _DP, ctypes.c_int, ctypes.POINTER(Gate)]),
+    "jq_gates_named": (ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(ctypes.c_char_p), _IP, _IP, _IP, _DP, _IP, _IP,
+                                      ctypes.POINTER(Gate)]),
     "jq_apply_gate": (ctypes.c_int, [_VP, ctypes.c_int, _IP, ctypes.c_int, _IP, ctypes.c_int, _DP]),
     "jq_apply_circuit": (ctypes.c_int, [_VP, ctypes.POINTER(Gate), ctypes.c_size_t, ctypes.POINTER(ExecOpts)]),
     "jq_apply_circuit_noalloc": (ctypes.c_int, [_VP, ctypes.POINTER(Gate), ctypes.c_size_t,
@@ -198,11 +200,22 @@ def gate(name, qubits, params=(), controls=()):
 
 
 def gates(circuit):
-    """Lower a list of (name, qubits, params[, controls]) tuples into a Gate array."""
-    arr = (Gate * max(1, len(circuit)))()
-    for i, g in enumerate(circuit):
-        arr[i] = gate(g[0], g[1], g[2], g[3] if len(g) > 3 else ())
-    return arr, len(circuit)
+    """Lower a list of (name, qubits, params[, controls]) tuples into a Gate
+    array (one jq_gates_named call)."""
+    n = len(circuit)
+    arr = (Gate * max(1, n))()
+    if n == 0:
+        return arr, 0
+    names = (ctypes.c_char_p * n)(*[g[0].encode() for g in circuit])
+    nq = np.fromiter((len(g[1]) for g in circuit), dtype=np.int32, count=n)
+    qs = np.fromiter((q for g in circuit for q in g[1]), dtype=np.int32)
+    npar = np.fromiter((len(g[2]) for g in circuit), dtype=np.int32, count=n)
+    ps = np.fromiter((p for g in circuit for p in g[2]), dtype=np.float64)
+    nc = np.fromiter((len(g[3]) if len(g) > 3 else 0 for g in circuit), dtype=np.int32, count=n)
+    cs = np.fromiter((c for g in circuit if len(g) > 3 for c in g[3]), dtype=np.int32)
+    check(lib().jq_gates_named(n, names, _ip(nq), _ip(qs) if qs.size else None, _ip(npar),
+                               _dp(ps) if ps.size else None, _ip(nc), _ip(cs) if cs.size else None, arr))
+    return arr, n
 
 
 def exec_opts(fusion=0, compact_mode=JQ_COMPACT_PER_GATE, max_ops=0, search=JQ_SEARCH_AUTO):

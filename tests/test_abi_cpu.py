@@ -125,3 +125,39 @@ def test_gate_struct_is_copied_controls_appended():
     g = jq.gate("H", [3], controls=[1, 2])
     assert g.nc == 2 and list(g.controls[:2]) == [1, 2]
     assert math.isclose(g.m[0], 1 / math.sqrt(2))
+
+
+def test_many_instructions_lower_in_one_call_as_one_by_one():
+    # jq_gates_named over a whole list gives the same records as
+    # jq_gate_named per instruction (controls appended after the name's)
+    from paper_1805_04708_amd import workloads as W
+    rng = np.random.default_rng(12)
+    circ = W.random_circuit(9, 300, 3) + W.layered_u2_cz(6, 3, 4)
+    circ += [("MAT1", (2,), tuple(float(x) for x in rng.normal(size=8)), (0, 5)), ("CNOT", (4, 1), (), (7,)),
+             ("I", (3,), ()), ("R", (2,), (3,)), ("TOFFOLI", (0, 1, 2), (), (3,)), ("U3", (1,), (0.1, 0.2, 0.3))]
+    arr, n = jq.gates(circ)
+    assert n == len(circ)
+    for i, g in enumerate(circ):
+        one = jq.gate(g[0], g[1], g[2], g[3] if len(g) > 3 else ())
+        assert bytes(arr[i]) == bytes(one), (i, g)
+
+
+def test_many_instructions_report_the_first_bad_index():
+    with pytest.raises(jq.JqError, match="instruction 2"):
+        jq.gates([("H", (0,), ()), ("X", (1,), ()), ("NOPE", (0,), ()), ("BAD", (0,), ())])
+    with pytest.raises(jq.JqError, match="instruction 1: .*takes"):
+        jq.gates([("H", (0,), ()), ("CNOT", (0,), ())])
+    with pytest.raises(jq.JqError, match="too many controls"):
+        jq.gates([("TOFFOLI", (0, 1, 2), (), (3, 4, 5))])
+    # zero counts take NULL arrays; an empty list is no call at all
+    out = (jq.Gate * 1)()
+    names = (ctypes.c_char_p * 1)(b"H")
+    one = np.array([1], dtype=np.int32)
+    zero = np.array([0], dtype=np.int32)
+    q = np.array([4], dtype=np.int32)
+    assert jq.lib().jq_gates_named(1, names, one.ctypes.data_as(jq._IP), q.ctypes.data_as(jq._IP),
+                                   zero.ctypes.data_as(jq._IP), None, None, None, out) == jq.JQ_OK
+    assert bytes(out[0]) == bytes(jq.gate("H", [4]))
+    assert jq.lib().jq_gates_named(1, names, one.ctypes.data_as(jq._IP), None, zero.ctypes.data_as(jq._IP),
+                                   None, None, None, out) == jq.JQ_EINVAL
+    assert jq.gates([])[1] == 0
