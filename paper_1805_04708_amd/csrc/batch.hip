@@ -278,12 +278,16 @@ __device__ void run_block(typename Vec<R>::T* S, int n, const BBlock& blk, const
 // tile's qubits (every op is linear, and its selectors and controls outside
 // the tile only choose among matrices): after passes 0..p-1 the state is
 // zero at every index with a bit set outside the union of their tile
-// qubits (the support).  So the first pass reads nothing: tile 0 (holding
-// index 0, in lane 0, slot 0) starts from its values, and every other tile
-// is zero before the pass and so after it, and is only written.  A later
-// pass skips every tile with an outer bit set outside the support: zero
-// before and after, and still zero in memory since the first pass wrote it.
-// The other (active) tiles are enumerated directly, spread over the waves.
+// qubits (the support).  A pass therefore runs only its active tiles, those
+// whose outer bits lie in the support (any other tile is zero before and
+// after it), enumerated directly and spread over the waves.  Memory holds
+// the state only inside the support: the arena is never cleared.  The
+// first pass's one active tile, tile 0 (index 0 in lane 0, slot 0), starts
+// from |0...0> in registers; a later pass reads only the amplitudes inside
+// the support and takes the others as zero.  Its active tiles cover every
+// index inside the new support, so the invariant holds after it.  At the
+// end, the indices outside the final support (qubits no pass held) are
+// written as zeros.
 template <typename R>
 __device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* __restrict__ passes, int n_passes,
                           const FOp* __restrict__ fops) {
@@ -313,41 +317,28 @@ __device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* __restric
             if ((support >> q) & 1) act |= 1ull << k;
             ++k;
         }
-        const uint64_t n_visit = p == 0 ? ntiles : 1ull << __builtin_popcountll(act);
+        const uint64_t n_visit = 1ull << __builtin_popcountll(act);
         for (uint64_t j = wave; j < n_visit; j += nw) {
-            // the first pass visits every tile; a later one the j-th active
-            // tile (j's bits deposited at the set bits of act)
-            uint64_t t = j;
-            if (p > 0) {
-                t = 0;
-                uint64_t jj = j;
-                for (uint64_t m = act; m; m &= m - 1, jj >>= 1)
-                    if (jj & 1) t |= m & (~m + 1);
-            }
+            // the j-th active tile: j's bits deposited at the set bits of act
+            uint64_t t = 0, jj = j;
+            for (uint64_t m = act; m; m &= m - 1, jj >>= 1)
+                if (jj & 1) t |= m & (~m + 1);
             uint64_t base = tile_base(P, t, lane_off);
             Cx<R> a[S];
             if (p == 0) {
-                if (t != 0) {
-#pragma unroll
-                    for (int s = 0; s < S; ++s) {
-                        uint64_t off = 0;
-#pragma unroll
-                        for (int j = 0; j < K; ++j)
-                            if (s & (1 << j)) off += stride[j];
-                        st<R>(psi, base + off, Cx<R>{(R)0, (R)0});
-                    }
-                    continue;
-                }
 #pragma unroll
                 for (int s = 0; s < S; ++s) a[s] = Cx<R>{(R)(s == 0 && lane == 0 ? 1 : 0), (R)0};
             } else {
+                const uint64_t outside = ~support;
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     uint64_t off = 0;
 #pragma unroll
                     for (int j = 0; j < K; ++j)
                         if (s & (1 << j)) off += stride[j];
-                    a[s] = ld<R>(psi, base + off);
+                    const uint64_t i = base + off;
+                    a[s] = Cx<R>{(R)0, (R)0};
+                    if (!(i & outside)) a[s] = ld<R>(psi, i);
                 }
             }
             run_ops<R, K>(a, ops, n_ops, base, wave_uniform(tile_base(P, t, 0)), lane);
@@ -363,6 +354,12 @@ __device__ void run_tiles(typename Vec<R>::T* psi, int n, const FPass* __restric
             }
         }
         support |= tmask;
+        __syncthreads();
+    }
+    const uint64_t outside = ~support & ((1ull << n) - 1);
+    if (outside) {
+        for (uint64_t i = threadIdx.x; i < (1ull << n); i += blockDim.x)
+            if (i & outside) st<R>(psi, i, Cx<R>{(R)0, (R)0});
         __syncthreads();
     }
 }
