@@ -131,9 +131,15 @@ typedef struct {
  *  pass_ops:    the planner's weight of one more pass against one more op
  *               in a pass (a pass's streaming time in units of one fused
  *               op's arithmetic), in (0, 10000];
- *  wide_target: per-gate dense and X kernels take four amplitude pairs per
- *               thread for targets from this qubit up, one below it (0..64;
- *               64: never);
+ *  wide_mask:   per-gate dense and X kernels take four amplitude pairs per
+ *               thread for each target whose bit is set, one pair for the
+ *               others (which is faster depends on the target's stride and
+ *               the device's address interleave: jq_autotune times both on
+ *               every target);
+ *  wide_target: the same choice as a threshold, for jq_tuning_set: with
+ *               wide_mask = 0 the targets from wide_target up (0..64; 64:
+ *               none) take four pairs.  jq_tuning_get reports the lowest
+ *               target in wide_mask (64: none);
  *  search:      the planner's large-state steps (see jq_exec_opts.search):
  *               JQ_SEARCH_AUTO (on from 1 GiB of state up), JQ_SEARCH_ON or
  *               JQ_SEARCH_OFF; an explicit opts->search wins;
@@ -165,6 +171,7 @@ typedef struct {
     double default_ms;
     int32_t search;
     int32_t reserved_;
+    uint64_t wide_mask;
 } jq_tuning;
 
 /* The tuning jq_apply_circuit uses for an N-qubit state of encoding enc on
@@ -187,9 +194,10 @@ int jq_tuning_set(int n_qubits, int enc, const jq_tuning *t);
  * planner weights, and the fastest set is kept if it beats the defaults
  * (among those timed) by 2% or more; the large-state steps are then timed
  * switched the other way than the size rule has them, and kept that way
- * under the same 2% rule; the per-gate threshold is the one
- * that minimises the summed time of a dense gate on every target from 8 up,
- * kept under the same 2% rule.  The tuning circuit is gates[0..count-1]
+ * under the same 2% rule; a dense gate on every target from 8 up is timed
+ * with one and with four pairs per thread, and a target takes four where
+ * that is 2% faster or more (the targets below 8, and from N up, keep the
+ * default and the highest timed target's choice).  The tuning circuit is gates[0..count-1]
  * (the caller's workload, validated as by jq_apply_circuit; the best
  * register width depends on a circuit's depth and structure), or, with
  * count = 0, ten layers of random U(2) on every qubit and CZ on a random

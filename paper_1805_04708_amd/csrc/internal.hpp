@@ -228,9 +228,9 @@ inline int bytes_per_amp(int enc) { return enc == JQ_C128 ? 16 : enc == JQ_C64 ?
 
 // state-vector (c128 / c64) launchers; psi is the device buffer
 void sv_init(int enc, void* psi, int n, int mode, uint64_t basis, hipStream_t st);
-// one op by its per-gate kernel; wide_target: dense and X targets from this
-// qubit up take four pairs per thread (one below it)
-void sv_apply_op(int enc, void* psi, int n, const GateOp& op, int wide_target, hipStream_t st);
+// one op by its per-gate kernel; wide_mask: dense and X targets whose bit is
+// set take four pairs per thread (the others one)
+void sv_apply_op(int enc, void* psi, int n, const GateOp& op, uint64_t wide_mask, hipStream_t st);
 // SHORBOX (App. A): 2^(-n_x/2) sum_x |x>|y^x mod G>, x on the n_x low qubits
 void sv_shorbox(int enc, void* psi, int n, int n_x, uint64_t G, uint64_t y, hipStream_t st);
 void sv_apply_fused(int enc, void* psi, int n, const FPass& pass, int k_reg, int fixed_lane_bits,

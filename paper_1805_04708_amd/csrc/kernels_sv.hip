@@ -420,9 +420,12 @@ unsigned grid_stride_blocks(uint64_t dim) {
 
 namespace {
 
-// wide_target: targets from this qubit up take four pairs per thread
+// wide_mask: targets whose bit is set take four pairs per thread, the
+// others one (measured at N=30 complex128: one pair is as fast or faster on
+// almost every target; complex64 differs target by target)
 template <typename R>
-void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, int wide_target, hipStream_t st) {
+void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, uint64_t wide_mask, hipStream_t st) {
+    const bool wide = (wide_mask >> op.t0) & 1;
     const int fixed = __builtin_popcountll(op.cmask);
     switch (op.kind) {
         case OP_DENSE1: {
@@ -434,7 +437,7 @@ void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, int wide_targe
             if (partial_lines<R>(op.cmask))
                 hipLaunchKernelGGL((k_dense1<R, 4, false>), dim3(chunk_blocks(ng, 4 * kBlock)), dim3(kBlock), 0, st,
                                    psi, ng, ins, tb, m, uint64_t(0));
-            else if (op.t0 < wide_target)
+            else if (!wide)
                 hipLaunchKernelGGL((k_dense1<R, 1, true>), dim3(chunk_blocks(ng, kBlock)), dim3(kBlock), 0, st, psi,
                                    ng, ins, tb, m, chunk_interleave<R>(ng, kBlock, op.cmask));
             else
@@ -482,7 +485,7 @@ void apply_op_t(typename Vec<R>::T* psi, int n, const GateOp& op, int wide_targe
             if (partial_lines<R>(op.cmask))
                 hipLaunchKernelGGL((k_permx<R, 4, false>), dim3(chunk_blocks(ng, 4 * kBlock)), dim3(kBlock), 0, st,
                                    psi, ng, ins, tb, uint64_t(0));
-            else if (op.t0 < wide_target)
+            else if (!wide)
                 hipLaunchKernelGGL((k_permx<R, 1, true>), dim3(chunk_blocks(ng, kBlock)), dim3(kBlock), 0, st, psi,
                                    ng, ins, tb, chunk_interleave<R>(ng, kBlock, op.cmask));
             else
@@ -553,9 +556,9 @@ void sv_shorbox(int enc, void* psi, int n, int n_x, uint64_t G, uint64_t y, hipS
     JQ_HIP(hipGetLastError());
 }
 
-void sv_apply_op(int enc, void* psi, int n, const GateOp& op, int wide_target, hipStream_t st) {
-    if (enc == JQ_C128) apply_op_t<double>((double2*)psi, n, op, wide_target, st);
-    else apply_op_t<float>((float2*)psi, n, op, wide_target, st);
+void sv_apply_op(int enc, void* psi, int n, const GateOp& op, uint64_t wide_mask, hipStream_t st) {
+    if (enc == JQ_C128) apply_op_t<double>((double2*)psi, n, op, wide_mask, st);
+    else apply_op_t<float>((float2*)psi, n, op, wide_mask, st);
 }
 
 void sv_apply_fused(int enc, void* psi, int n, const FPass& pass, int k_reg, int fixed_lane_bits, hipStream_t st) {

@@ -244,7 +244,7 @@ void run_single(jq_state* s, const GateOp& op) {
     {
         Timed t(s, kclass(op, s->enc), op_bytes(op, s->n, s->enc));
         if (s->enc == JQ_COMPACT) cp_apply_op(compact_bufs(s), s->n, op, s->stream);
-        else sv_apply_op(s->enc, s->buf, s->n, op, tuned_for(s->n, s->enc).wide_target, s->stream);
+        else sv_apply_op(s->enc, s->buf, s->n, op, tuned_for(s->n, s->enc).wide_mask, s->stream);
     }
     blocking_check(s, "per-gate kernel");
 }

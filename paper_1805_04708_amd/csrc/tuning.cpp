@@ -1,7 +1,7 @@
 // Tuning of the single-state path (jq_tuning_get / jq_tuning_set /
 // jq_autotune): the fused pass's register width, the planner's weight of a
-// pass against its ops, and the per-gate kernels' wide-target threshold,
-// per (device, encoding, N).  Values come from this process (set or
+// pass against its ops, and the per-gate kernels' width per target (one or
+// four amplitude pairs per thread), per (device, encoding, N).  Values come from this process (set or
 // measured), else from a JSON cache file, else built-in defaults.
 #include <algorithm>
 #include <cctype>
@@ -98,8 +98,11 @@ std::string device_key() {
 // --------------------------------------------------------- cache file --
 //
 // {"version": 1, "entries": [{"device": "...", "encoding": "c128", "n": 28,
-//   "k_reg": 4, "pass_ops": 19.0, "wide_target": 17, "tuned_ms": ..,
-//   "default_ms": ..}, ...]}
+//   "k_reg": 4, "pass_ops": 19.0, "wide_target": 17, "wide_mask": 1966080,
+//   "tuned_ms": .., "default_ms": ..}, ...]}
+// wide_mask is optional (entries without it take the targets from
+// wide_target up) and holds targets below 53 only, so that the number is
+// exact as a double.
 //
 // The reader accepts exactly this shape (objects of string and number
 // fields inside "entries"); anything else makes the whole file count as
@@ -146,6 +149,16 @@ struct Reader {
 
 bool valid(int enc, const jq_tuning& t);
 
+constexpr uint64_t kMaskJson = (1ull << 53) - 1;
+
+// Make wide_mask and wide_target agree: a zero mask stands for the targets
+// from wide_target up; wide_target becomes the mask's lowest target (64:
+// none).
+void normalize_wide(jq_tuning& t) {
+    if (t.wide_mask == 0) t.wide_mask = t.wide_target >= 64 ? 0 : ~0ull << t.wide_target;
+    t.wide_target = t.wide_mask ? __builtin_ctzll(t.wide_mask) : 64;
+}
+
 bool parse_entry(Reader& r, Entry& e) {
     if (!r.eat('{')) return false;
     bool have_dev = false, have_enc = false, have_n = false, have_k = false, have_p = false, have_w = false;
@@ -170,6 +183,7 @@ bool parse_entry(Reader& r, Entry& e) {
             else if (key == "k_reg") e.t.k_reg = (int)v, have_k = v == std::floor(v);
             else if (key == "pass_ops") e.t.pass_ops = v, have_p = true;
             else if (key == "wide_target") e.t.wide_target = (int)v, have_w = v == std::floor(v);
+            else if (key == "wide_mask") e.t.wide_mask = (uint64_t)v;
             else if (key == "search") e.t.search = (int)v;
             else if (key == "tuned_ms") e.t.tuned_ms = v;
             else if (key == "default_ms") e.t.default_ms = v;
@@ -179,7 +193,9 @@ bool parse_entry(Reader& r, Entry& e) {
     if (!(have_dev && have_enc && have_n && have_k && have_p && have_w)) return false;
     e.t.n_qubits = e.n;
     e.t.source = JQ_TUNE_CACHED;
-    return e.n >= 1 && e.n <= JQ_MAX_QUBITS && valid(e.enc, e.t);
+    if (!(e.n >= 1 && e.n <= JQ_MAX_QUBITS && valid(e.enc, e.t))) return false;
+    normalize_wide(e.t);  // an entry without wide_mask: from wide_target
+    return true;
 }
 
 std::vector<Entry> read_cache_file(const std::string& path) {
@@ -235,10 +251,11 @@ void write_cache_file(const std::string& path, const std::vector<Entry>& entries
             char buf[512];
             std::snprintf(buf, sizeof buf,
                           "%s\n  {\"device\": \"%s\", \"encoding\": \"%s\", \"n\": %d, \"k_reg\": %d, "
-                          "\"pass_ops\": %.17g, \"wide_target\": %d, \"search\": %d, \"tuned_ms\": %.17g, "
-                          "\"default_ms\": %.17g}",
+                          "\"pass_ops\": %.17g, \"wide_target\": %d, \"wide_mask\": %llu, \"search\": %d, "
+                          "\"tuned_ms\": %.17g, \"default_ms\": %.17g}",
                           i ? "," : "", e.device.c_str(), enc_name(e.enc), e.n, e.t.k_reg, e.t.pass_ops,
-                          e.t.wide_target, e.t.search, e.t.tuned_ms, e.t.default_ms);
+                          e.t.wide_target, (unsigned long long)(e.t.wide_mask & kMaskJson), e.t.search,
+                          e.t.tuned_ms, e.t.default_ms);
             f << buf;
         }
         f << "\n]}\n";
@@ -298,11 +315,15 @@ jq_tuning default_tuning(int enc) {
     jq_tuning t{};
     // measured on an MI355X at N = 30 (see the planner's cost model):
     // complex128 K = 4 (occupancy 4), complex64 K = 5; a pass streams in the
-    // time of 19 (complex128) or 6 (complex64) ops; the four-pairs-per-thread
-    // per-gate kernels win from target 17 up (strides of 2 MiB and more)
+    // time of 19 (complex128) or 6 (complex64) ops; the per-gate kernels
+    // take one pair per thread on every complex128 target (as fast or within
+    // 2.5% everywhere, up to 12% faster from target 17 up), and four from
+    // target 17 up for complex64, where the better width changes target by
+    // target (the tuner chooses per target)
     t.k_reg = enc == JQ_C64 ? 5 : 4;
     t.pass_ops = enc == JQ_C64 ? 6.0 : 19.0;
-    t.wide_target = 17;
+    t.wide_mask = enc == JQ_C64 ? ~0ull << 17 : 0;
+    t.wide_target = enc == JQ_C64 ? 17 : 64;
     t.search = JQ_SEARCH_AUTO;  // on from 1 GiB of state up (the planner's size rule)
     t.n_qubits = 0;
     t.source = JQ_TUNE_DEFAULT;
@@ -468,36 +489,29 @@ jq_tuning measure(int n, int enc, const std::vector<GateOp>& workload) {
         }
     }
 
-    // per-gate threshold: one dense gate on every target from 8 up with one
-    // pair per thread and with four; the threshold minimising the sum
+    // per-gate widths: one dense gate on every target from 8 up with one
+    // pair per thread (mask 0) and with four (every bit set)
     const int lo = std::min(8, n - 1);
     std::vector<double> t1(n, 0.0), t4(n, 0.0);
     for (int t = lo; t < n; ++t) {
         GateOp op = probe[t];  // the U(2) on qubit t
-        for (int wide : {64, 0}) {
+        for (const uint64_t wide : {uint64_t(0), ~uint64_t(0)}) {
             sv_apply_op(enc, s->buf, n, op, wide, s->stream);  // warm
             double v = 1e30;
             for (int r = 0; r < 3; ++r)
                 v = std::min(v, tm.ms(s->stream, [&] { sv_apply_op(enc, s->buf, n, op, wide, s->stream); }));
-            (wide == 64 ? t1 : t4)[t] = v;
+            (wide ? t4 : t1)[t] = v;
         }
     }
-    auto summed = [&](int w) {
-        double sum = 0.0;
-        for (int t = lo; t < n; ++t) sum += t < w ? t1[t] : t4[t];
-        return sum;
-    };
-    int best_w = def.wide_target;
-    const double def_sum = summed(def.wide_target);
-    double best_sum = def_sum;
-    for (int w = lo; w <= n; ++w) {
-        const double sum = summed(w);
-        if (sum < best_sum) {
-            best_sum = sum;
-            best_w = w == n ? 64 : w;
-        }
-    }
-    best.wide_target = best_sum < kMargin * def_sum ? best_w : def.wide_target;
+    // below lo the default; from lo up four pairs where they are 2% faster;
+    // from n up (a larger state using this entry) as on target n - 1
+    uint64_t mask = def.wide_mask & ((1ull << lo) - 1);
+    for (int t = lo; t < n; ++t)
+        if (t4[t] < kMargin * t1[t]) mask |= 1ull << t;
+    if ((mask >> (n - 1)) & 1) mask |= ~0ull << n;
+    best.wide_mask = mask;
+    best.wide_target = 0;
+    normalize_wide(best);
     best.n_qubits = n;
     best.source = JQ_TUNE_MEASURED;
     best.tuned_ms = best_ms;
@@ -542,6 +556,7 @@ int jq_tuning_set(int n_qubits, int enc, const jq_tuning* t) {
         e.t = *t;
         e.t.n_qubits = n_qubits;
         e.t.source = JQ_TUNE_SET;
+        normalize_wide(e.t);
         upsert(g_process, e);
     });
 }

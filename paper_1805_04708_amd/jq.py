@@ -43,7 +43,8 @@ class Gate(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("k_reg", ctypes.c_int32), ("wide_target", ctypes.c_int32), ("pass_ops", ctypes.c_double),
                 ("n_qubits", ctypes.c_int32), ("source", ctypes.c_int32), ("tuned_ms", ctypes.c_double),
-                ("default_ms", ctypes.c_double), ("search", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("default_ms", ctypes.c_double), ("search", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("wide_mask", ctypes.c_uint64)]
 
 
 class ExecOpts(ctypes.Structure):
@@ -244,8 +245,8 @@ _TUNE_SOURCES = {JQ_TUNE_DEFAULT: "default", JQ_TUNE_MEASURED: "measured", JQ_TU
 
 
 def _tuning_dict(t):
-    return {"k_reg": t.k_reg, "wide_target": t.wide_target, "pass_ops": t.pass_ops, "search": t.search,
-            "n_qubits": t.n_qubits,
+    return {"k_reg": t.k_reg, "wide_target": t.wide_target, "wide_mask": t.wide_mask, "pass_ops": t.pass_ops,
+            "search": t.search, "n_qubits": t.n_qubits,
             "source": _TUNE_SOURCES.get(t.source, t.source), "tuned_ms": t.tuned_ms, "default_ms": t.default_ms}
 
 
@@ -256,8 +257,9 @@ def tuning_get(n, enc):
     return _tuning_dict(t)
 
 
-def tuning_set(n, enc, k_reg=None, wide_target=None, pass_ops=None, search=None, clear=False):
-    """Override (jq_tuning_set) fields of the current tuning; clear=True removes an override."""
+def tuning_set(n, enc, k_reg=None, wide_target=None, pass_ops=None, search=None, clear=False, wide_mask=None):
+    """Override (jq_tuning_set) fields of the current tuning; clear=True removes an override.
+    wide_target sets the per-gate width as a threshold, wide_mask target by target."""
     if clear:
         check(lib().jq_tuning_set(n, ENCODINGS.get(enc, enc), None))
         return
@@ -267,6 +269,9 @@ def tuning_set(n, enc, k_reg=None, wide_target=None, pass_ops=None, search=None,
         t.k_reg = k_reg
     if wide_target is not None:
         t.wide_target = wide_target
+        t.wide_mask = 0  # from the threshold
+    if wide_mask is not None:
+        t.wide_mask = wide_mask
     if pass_ops is not None:
         t.pass_ops = pass_ops
     if search is not None:

@@ -49,6 +49,10 @@ def test_autotune_measures_caches_and_matches_the_oracle(enc, _cache):
     data = json.loads(_cache.read_text())
     (e,) = [x for x in data["entries"] if x["n"] == n and x["encoding"] == enc]
     assert e["device"] != "host" and e["k_reg"] == t["k_reg"] and e["wide_target"] == t["wide_target"]
+    # the per-target widths: chosen from target 8 up, the file holding the
+    # targets below 53
+    assert e["wide_mask"] == t["wide_mask"] & (2**53 - 1)
+    assert t["wide_target"] == (64 if t["wide_mask"] == 0 else (t["wide_mask"] & -t["wide_mask"]).bit_length() - 1)
     jq.tuning_set(n, enc, clear=True)
     c = jq.autotune(n, enc)
     assert c["source"] == "cached" and c["k_reg"] == t["k_reg"]
@@ -77,9 +81,14 @@ def test_every_tuned_value_keeps_oracle_parity(enc):
             with jq.State(n, enc) as s:
                 s.apply_circuit(circ)
                 assert O.rel_l2(s.amplitudes(), ref) <= TOL[enc] * 2, (k, ops)
-    # per-gate kernels: one pair per thread everywhere, four everywhere
+    # per-gate kernels: one pair per thread everywhere, four everywhere,
+    # from target 9 up, and a mask that alternates target by target
     for wide in (0, 64, 9):
         jq.tuning_set(n, enc, wide_target=wide)
         with jq.State(n, enc) as s:
             s.apply_circuit(circ, fusion=1)
             assert O.rel_l2(s.amplitudes(), ref) <= TOL[enc] * 2, wide
+    jq.tuning_set(n, enc, wide_mask=int("01" * 16, 2))
+    with jq.State(n, enc) as s:
+        s.apply_circuit(circ, fusion=1)
+        assert O.rel_l2(s.amplitudes(), ref) <= TOL[enc] * 2

@@ -33,9 +33,11 @@ def write(path, entries, version=1):
 
 
 def test_defaults_without_a_cache_file():
-    for enc, k, ops in (("c128", 4, 19.0), ("c64", 5, 6.0)):
+    # complex128: one pair per thread on every target; complex64: four from 17 up
+    for enc, k, ops, wide, mask in (("c128", 4, 19.0, 64, 0), ("c64", 5, 6.0, 17, (2**64 - 1) ^ (2**17 - 1))):
         t = jq.tuning_get(30, enc)
-        assert (t["k_reg"], t["pass_ops"], t["wide_target"], t["source"]) == (k, ops, 17, "default")
+        assert (t["k_reg"], t["pass_ops"], t["wide_target"], t["wide_mask"], t["source"]) == \
+            (k, ops, wide, mask, "default")
 
 
 def test_cache_exact_size_and_streaming_fallback(_cache):
@@ -129,3 +131,24 @@ def test_autotune_needs_a_device():
     with pytest.raises(jq.JqError) as e:  # an invalid workload gate
         jq.autotune(12, "c128", [("CNOT", (3, 3), ())])
     assert e.value.code == jq.JQ_EINVAL
+
+
+def test_per_target_width_mask(_cache):
+    # an entry without wide_mask takes the targets from wide_target up; one
+    # with a mask keeps it (and reports its lowest target); the file written
+    # by the tuner round-trips the mask
+    low = 2**53 - 1
+    write(_cache, [entry(26, wide=12), dict(entry(28, wide=12), wide_mask=(1 << 9) | (1 << 20) | (1 << 21))])
+    t = jq.tuning_get(26, "c128")
+    assert t["wide_mask"] & low == low ^ (2**12 - 1) and t["wide_target"] == 12
+    t = jq.tuning_get(28, "c128")
+    assert t["wide_mask"] == (1 << 9) | (1 << 20) | (1 << 21) and t["wide_target"] == 9
+    # set: a threshold, then a mask, then none at all
+    jq.tuning_set(28, "c128", wide_target=20)
+    t = jq.tuning_get(28, "c128")
+    assert t["wide_target"] == 20 and t["wide_mask"] == (2**64 - 1) ^ (2**20 - 1)
+    jq.tuning_set(28, "c128", wide_mask=(1 << 5) | (1 << 27))
+    t = jq.tuning_get(28, "c128")
+    assert (t["wide_target"], t["wide_mask"], t["source"]) == (5, (1 << 5) | (1 << 27), "set")
+    jq.tuning_set(28, "c128", wide_target=64)
+    assert (jq.tuning_get(28, "c128")["wide_mask"], jq.tuning_get(28, "c128")["wide_target"]) == (0, 64)
