@@ -410,8 +410,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(typename Vec<R>::T* __r
 
 // Tile-mode circuits (states in the arena): the same work counter scheme,
 // no LDS, so more workgroups fit per compute unit than in the block kernel.
+// Held to 128 VGPRs (4 waves per SIMD; the complex128 kernel spills 68
+// bytes, which costs less than running 3 waves: measured 0.97 vs 1.02 ms
+// per 4096-circuit launch).
 template <typename R>
-__global__ __launch_bounds__(kBatchThreads) void k_batch_tiles(typename Vec<R>::T* __restrict__ arena,
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_tiles(typename Vec<R>::T* __restrict__ arena,
                                                                 const BCirc* __restrict__ circs,
                                                                 const int32_t* __restrict__ order, uint32_t count,
                                                                 const FPass* __restrict__ passes,
