@@ -122,8 +122,11 @@ def single_gate_cases(n, rng):
 
 
 @pytest.mark.parametrize("enc", ["c128", "c64"])
-@pytest.mark.parametrize("n", [1, 2, 3, 6, 7, 11, 14])
+@pytest.mark.parametrize("n", [1, 2, 3, 6, 7, 8, 11, 14])
 def test_every_gate_class_every_target(enc, n):
+    # N = 8 is the smallest state whose uncontrolled gates on targets 0-2 run
+    # the lane-exchange kernel (one chunk of 256 amplitudes); below it they
+    # run the pair kernel
     rng = np.random.default_rng(1000 + n)
     psi0 = rand_state(rng, n)
     for g in single_gate_cases(n, rng):
