@@ -918,8 +918,10 @@ __global__ __launch_bounds__(kBlock) void k_cp_codes(int8_t* __restrict__ b0, in
 #pragma unroll
         for (int j = 2; j < K; ++j)
             if (sh & (1 << j)) off += stride[j];
-        const uint32_t x0 = *reinterpret_cast<const uint32_t*>(b0 + off + lane_b);
-        const uint32_t x1 = *reinterpret_cast<const uint32_t*>(b1 + off + lane_b);
+        // every code is read and written once per pass: non-temporal (measured
+        // 14.60 -> 13.98 ms per pass at N=34, 102.0 -> 100.8 ms at N=37)
+        const uint32_t x0 = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(b0 + off + lane_b));
+        const uint32_t x1 = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(b1 + off + lane_b));
         // bytes (b0, b1) of slots sh, sh+1 and of sh+2, sh+3
         c[sh / 2] = __builtin_amdgcn_perm(x1, x0, 0x05010400u);
         c[sh / 2 + 1] = __builtin_amdgcn_perm(x1, x0, 0x07030602u);
@@ -961,8 +963,8 @@ __global__ __launch_bounds__(kBlock) void k_cp_codes(int8_t* __restrict__ b0, in
         const uint32_t t = y0 ^ 0x80808080u;
         const uint32_t z = ~(((t & 0x7f7f7f7fu) + 0x7f7f7f7fu) | t) & 0x80808080u;
         y1 &= ~(z | (z - (z >> 7)));
-        *reinterpret_cast<uint32_t*>(b0 + off + lane_b) = y0;
-        *reinterpret_cast<uint32_t*>(b1 + off + lane_b) = y1;
+        __builtin_nontemporal_store(y0, reinterpret_cast<uint32_t*>(b0 + off + lane_b));
+        __builtin_nontemporal_store(y1, reinterpret_cast<uint32_t*>(b1 + off + lane_b));
     }
     }
 }
