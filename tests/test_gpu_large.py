@@ -285,12 +285,23 @@ def test_n34_per_gate_kernels_on_the_full_grid():
         pytest.skip("needs 256 GiB of free HBM")
     with jq.State(n, "c128") as s:
         s.init(jq.JQ_INIT_UNIFORM)
-        theta = 0.8
-        s.apply_circuit([("RZ", (5,), (theta,)), ("CNOT", (3, 33), ()), ("H", (7,), ())], fusion=1)
+        theta, phi, psi = 0.8, 0.3, 1.1
+        # qubits 0-2 take the lane-exchange kernels (dense and X), whose
+        # capped grid loops 16 times over the 2^26 chunks of 256 amplitudes
+        s.apply_circuit([("RZ", (5,), (theta,)), ("CNOT", (3, 33), ()), ("H", (7,), ()),
+                         ("RZ", (1,), (phi,)), ("X", (1,), ()), ("RZ", (2,), (psi,)), ("H", (2,), ()),
+                         ("H", (0,), ())], fusion=1)
         amp = 2.0 ** (-n / 2)
-        for i in [0, 1 << 5, (1 << n) - 1, 987654321]:
-            # H on qubit 7 of a uniform state: sqrt(2) amp on bit 7 = 0, 0 on bit 7 = 1
-            want = 0.0 if (i >> 7) & 1 else math.sqrt(2) * amp
-            want *= np.exp(-0.5j * theta) if not (i >> 5) & 1 else np.exp(0.5j * theta)
+        r2 = math.sqrt(2)
+        for i in [0, 1 << 5, 2, 4, 6, 0b100110, (1 << n) - 1, (1 << n) - 1 - 0b10000001, 987654321, 987654320]:
+            b = [(i >> q) & 1 for q in range(8)]
+            # the state stays a product over qubits: CNOT(3, 33) leaves a
+            # state uniform in both of its qubits unchanged
+            want = amp
+            want *= np.exp(0.5j * theta) if b[5] else np.exp(-0.5j * theta)
+            want *= 0.0 if b[7] else r2  # H on a uniform qubit
+            want *= 0.0 if b[0] else r2
+            want *= np.exp(-0.5j * phi) if b[1] else np.exp(0.5j * phi)  # X swaps the RZ phases
+            want *= -1j * r2 * math.sin(psi / 2) if b[2] else r2 * math.cos(psi / 2)
             assert abs(s.amplitudes(i, 1)[0] - want) < 1e-15, i
         assert abs(s.norm() - 1.0) < 1e-12
