@@ -32,6 +32,15 @@ __device__ __forceinline__ M2x2<R> load_m_v(const FOp* op, int v) {
     return {{(R)m[0], (R)m[1]}, {(R)m[2], (R)m[3]}, {(R)m[4], (R)m[5]}, {(R)m[6], (R)m[7]}};
 }
 
+// Matrix v read per lane (v may differ between lanes): four 16-byte vector
+// loads from the op record (FOp::m is 16-byte aligned, see internal.hpp).
+template <typename R>
+__device__ __forceinline__ M2x2<R> load_m_lane(const FOp* op, int v) {
+    const double2* m = reinterpret_cast<const double2*>(op->m) + 4 * v;
+    const double2 e0 = m[0], e1 = m[1], e2 = m[2], e3 = m[3];
+    return {{(R)e0.x, (R)e0.y}, {(R)e1.x, (R)e1.y}, {(R)e2.x, (R)e2.y}, {(R)e3.x, (R)e3.y}};
+}
+
 template <typename R>
 __device__ __forceinline__ M2x2<R> msel(bool c, const M2x2<R>& x, const M2x2<R>& y) {
     return {csel(c, x.m0, y.m0), csel(c, x.m1, y.m1), csel(c, x.m2, y.m2), csel(c, x.m3, y.m3)};
@@ -42,6 +51,11 @@ __device__ __forceinline__ M2x2<R> msel(bool c, const M2x2<R>& x, const M2x2<R>&
 // An outer bit is the same in every lane of the wave (read from the tile
 // base ubase), so its part of the choice is made once for the wave, with
 // the matrix read by scalar loads; only lane-bit selectors choose per lane.
+// One lane selector chooses between two scalar-loaded matrices in
+// registers.  With two, the matrix is loaded per lane instead: a chain of
+// three selects held two candidate sets live at once and set the fused
+// kernel's peak register count (98 instead of 94 VGPRs for complex128 with
+// the op set of kLiteKinds).
 template <typename R>
 __device__ __forceinline__ M2x2<R> mux_thread(const FOp* op, uint64_t base, uint64_t ubase) {
     const int lm = op->sel_lane;
@@ -60,11 +74,7 @@ __device__ __forceinline__ M2x2<R> mux_thread(const FOp* op, uint64_t base, uint
         const int v1 = (int)((ubase >> s1) & 1);
         return msel(((base >> s0) & 1) != 0, load_m_v<R>(op, 2 + v1), load_m_v<R>(op, v1));
     }
-    const int v = 2 * (int)((base >> s0) & 1) + (int)((base >> s1) & 1);
-    M2x2<R> m = load_m_v<R>(op, 0);
-    m = msel(v == 1, load_m_v<R>(op, 1), m);
-    m = msel(v == 2, load_m_v<R>(op, 2), m);
-    return msel(v == 3, load_m_v<R>(op, 3), m);
+    return load_m_lane<R>(op, 2 * (int)((base >> s0) & 1) + (int)((base >> s1) & 1));
 }
 
 // Multiplexed 2x2 on register slot J: the matrix depends on 1-2 selector
@@ -208,6 +218,16 @@ __device__ __forceinline__ void lane_op_b(Cx<R> (&a)[1 << K], const FOp* op, int
     }
 }
 
+// x with its sign bit XORed with bit 31 of f (f is 0 or 0x80000000):
+// -x bit for bit when f is set, x otherwise
+__device__ __forceinline__ double flip_sign(double x, uint32_t f) {
+    const uint64_t b = (uint64_t)__builtin_bit_cast(uint64_t, x) ^ ((uint64_t)f << 32);
+    return __builtin_bit_cast(double, b);
+}
+__device__ __forceinline__ float flip_sign(float x, uint32_t f) {
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x) ^ f);
+}
+
 // Multiply the controlled subset by d0 (F_PHASE) or negate it (F_NEG).  The
 // thread's part of the control test is folded into a per-thread factor
 // once; the register part is uniform per slot and becomes a branch.
@@ -215,20 +235,16 @@ template <typename R, int K, bool NEG>
 __device__ __forceinline__ void phase_op(Cx<R> (&a)[1 << K], const FOp* op, bool thr_ok) {
     const uint32_t rc = op->reg_ctrl;
     if constexpr (NEG) {
-        const R sg = thr_ok ? (R)-1 : (R)1;
-        if (rc == 0) {
+        // negation flips the sign bit, the same bits as a product with -1
+        // (signed zeros and NaNs included), with no factor per slot held
+        // in registers
+        const uint32_t sgn = thr_ok ? 0x80000000u : 0u;
 #pragma unroll
-            for (int s = 0; s < (1 << K); ++s) {
-                a[s].re *= sg;
-                a[s].im *= sg;
-            }
-        } else {
-#pragma unroll
-            for (int s = 0; s < (1 << K); ++s) {
-                const R f = (((uint32_t)s & rc) == rc) ? sg : (R)1;
-                a[s].re *= f;
-                a[s].im *= f;
-            }
+        for (int s = 0; s < (1 << K); ++s) {
+            const uint32_t f = (((uint32_t)s & rc) == rc) ? sgn : 0u;
+            a[s].re = flip_sign(a[s].re, f);
+            a[s].im = flip_sign(a[s].im, f);
+            if ((s & 3) == 3) JQ_SLOT_FENCE();
         }
     } else {
         const Cx<R> d{(R)op->m[0], (R)op->m[1]};
@@ -461,7 +477,17 @@ __device__ __forceinline__ void st_stream(typename Vec<R>::T* p, uint64_t i, Cx<
 
 // base: index of the lane's first amplitude; ubase: the tile's base, the
 // same in every lane (base without the lane bits)
-template <typename R, int K>
+// Op kinds of the reduced op loop (LITE): dense and multiplexed 2x2s on
+// register slots and lane bits, and negations; what layers of one-qubit
+// gates with CZs between them lower to.  A kernel compiled with every kind
+// needs as many registers as its hungriest kind plus what the others keep
+// live across the loop (121 VGPRs for complex128 with 2^4 register slots,
+// 4 waves per SIMD); one compiled with these alone needs 94 (5 waves).
+constexpr uint32_t kLiteKinds = (1u << F_DENSE_REG) | (1u << F_DENSE_LANE) | (1u << F_MDENSE_REG) |
+                                (1u << F_MDENSE_LANE) | (1u << F_NEG);
+
+// LITE: the op list holds only kinds of kLiteKinds (others are skipped).
+template <typename R, int K, bool LITE = false>
 __device__ __forceinline__ void run_ops(Cx<R> (&a)[1 << K], const FOp* __restrict__ ops, int n_ops, uint64_t base,
                                         uint64_t ubase, int lane) {
     for (int k = 0; k < n_ops; ++k) {
@@ -472,19 +498,19 @@ __device__ __forceinline__ void run_ops(Cx<R> (&a)[1 << K], const FOp* __restric
                 reg_dispatch<R, K, F_DENSE_REG>(a, op, thr_ok, base, ubase);
                 break;
             case F_CDENSE_REG:
-                reg_dispatch<R, K, F_CDENSE_REG>(a, op, thr_ok, base, ubase);
+                if constexpr (!LITE) reg_dispatch<R, K, F_CDENSE_REG>(a, op, thr_ok, base, ubase);
                 break;
             case F_PERM_REG:
-                reg_dispatch<R, K, F_PERM_REG>(a, op, thr_ok, base, ubase);
+                if constexpr (!LITE) reg_dispatch<R, K, F_PERM_REG>(a, op, thr_ok, base, ubase);
                 break;
             case F_DENSE_LANE:
                 lane_dispatch<R, K, F_DENSE_LANE>(a, op, lane, thr_ok);
                 break;
             case F_CDENSE_LANE:
-                lane_dispatch<R, K, F_CDENSE_LANE>(a, op, lane, thr_ok);
+                if constexpr (!LITE) lane_dispatch<R, K, F_CDENSE_LANE>(a, op, lane, thr_ok);
                 break;
             case F_PERM_LANE:
-                lane_dispatch<R, K, F_PERM_LANE>(a, op, lane, thr_ok);
+                if constexpr (!LITE) lane_dispatch<R, K, F_PERM_LANE>(a, op, lane, thr_ok);
                 break;
             case F_MDENSE_REG:
                 reg_dispatch<R, K, F_MDENSE_REG>(a, op, thr_ok, base, ubase);
@@ -493,16 +519,16 @@ __device__ __forceinline__ void run_ops(Cx<R> (&a)[1 << K], const FOp* __restric
                 lane_dispatch<R, K, F_MDENSE_LANE>(a, op, lane, thr_ok, base, ubase);
                 break;
             case F_PHASE:
-                phase_op<R, K, false>(a, op, thr_ok);
+                if constexpr (!LITE) phase_op<R, K, false>(a, op, thr_ok);
                 break;
             case F_NEG:
                 phase_op<R, K, true>(a, op, thr_ok);
                 break;
             case F_DIAG:
-                diag_op<R, K>(a, op, base, ubase, thr_ok);
+                if constexpr (!LITE) diag_op<R, K>(a, op, base, ubase, thr_ok);
                 break;
             case F_DGROUP:
-                dgroup_op<R, K>(a, op, lane, ubase);
+                if constexpr (!LITE) dgroup_op<R, K>(a, op, lane, ubase);
                 break;
             default:
                 break;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <deque>
@@ -148,6 +149,9 @@ struct FOp {
     double od_m[4 * kMaxOdiag];
 };
 
+// the fused kernels read FOp::m with 16-byte vector loads per lane
+static_assert(offsetof(FOp, m) % 16 == 0 && sizeof(FOp) % 16 == 0, "FOp::m must stay 16-byte aligned in an array");
+
 constexpr int kMaxTileBits = 16;
 
 struct FPass {
@@ -157,6 +161,7 @@ struct FPass {
     int32_t tile_sorted[kMaxTileBits];
     int32_t n_ops;
     int32_t table_tag;   // the tag of the pass's F_DGROUP register tables (0: none)
+    uint32_t kinds;      // bit k: the pass holds an op of kind k (0: not recorded, any kind)
     const FOp* ops;      // device pointer
 };
 

@@ -760,6 +760,8 @@ Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const Step
             ++n_ops;
         }
         s.pass.n_ops = n_ops;
+        s.pass.kinds = 0;
+        for (size_t i = s.first_fop; i < plan.fops.size(); ++i) s.pass.kinds |= 1u << plan.fops[i].kind;
         s.n_gates = pb.taken.size();
         s.gates = pb.taken;
         emit(std::move(s));
