@@ -207,6 +207,12 @@ struct PlanConfig {
     // diagonal tables, up to 16 slots) or 4 (complex64: float pairs, up to
     // 32); make_plan rejects other values
     int table_elem = 8;
+    // widest register width at which the fused kernel compiled for every op
+    // kind keeps 4 waves per SIMD (0: no limit); make_plan narrows a wider
+    // k_reg to it unless every gate lowers to the reduced kind set, or the
+    // caller asked for the width (k_explicit)
+    int k_general_max = 0;
+    bool k_explicit = false;
 };
 
 struct Plan {

@@ -452,7 +452,29 @@ void merge_same_target(std::vector<PassOp>& ops) {
 
 }  // namespace
 
-Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg, const StepSink& on_step) {
+namespace {
+
+// A gate that every fused pass lowers to an op of kLiteKinds: an
+// uncontrolled one-qubit dense gate (a 2x2, or a multiplexed 2x2 once
+// diagonals fold into it) or a controlled Z on two or more qubits (a
+// negation, or a selector of a multiplexed 2x2).
+bool lowers_to_reduced_kinds(const GateOp& op) {
+    if (op.kind == OP_DENSE1) return op.cmask == 0;
+    return op.kind == OP_DIAG && op.nsel == 0 && __builtin_popcountll(op.cmask) >= 2 && op.m[0].re == -1.0 &&
+           op.m[0].im == 0.0;
+}
+
+}  // namespace
+
+Plan make_plan(const std::vector<GateOp>& ops, const PlanConfig& cfg_in, const StepSink& on_step) {
+    // Passes that hold any other op run the kernel compiled for every kind,
+    // whose registers at a wider width leave 2-3 waves per SIMD (complex128
+    // with 2^5 slots: 217 VGPRs, passes twice as slow as with 2^4): keep
+    // such circuits at the width where it still runs 4.
+    PlanConfig cfg = cfg_in;
+    if (cfg.fuse && !cfg.k_explicit && cfg.k_general_max > 0 && cfg.k_reg > cfg.k_general_max &&
+        !std::all_of(ops.begin(), ops.end(), lowers_to_reduced_kinds))
+        cfg.k_reg = cfg.k_general_max;
     Plan plan;
     auto emit = [&](Step&& s) {
         plan.steps.push_back(std::move(s));

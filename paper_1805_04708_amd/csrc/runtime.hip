@@ -267,6 +267,7 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
     // two-byte code's decoding passes are taken as complex128's
     const jq_tuning tune = compact ? default_tuning(JQ_C128) : tuned_for(n, enc);
     c.k_reg = compact ? 4 : tune.k_reg;
+    c.k_general_max = compact ? 0 : enc == JQ_C64 ? 5 : 4;
     c.pass_ops = tune.pass_ops;
     c.table_elem = enc == JQ_C64 ? 4 : 8;
     // the tile-slot search costs about 0.1 ms of host time per pass: worth
@@ -281,7 +282,7 @@ PlanConfig plan_config(int n, int enc, const jq_exec_opts* opts) {
             fail(JQ_EINVAL, "jq_exec_opts: bad compact_mode");
         if (compact && opts->compact_mode == JQ_COMPACT_PER_BLOCK) c.code_domain = false;
         if (opts->fusion == 1) c.fuse = false;
-        else if (opts->fusion >= 2) c.k_reg = std::min(opts->fusion, c.code_domain ? 7 : k_max);
+        else if (opts->fusion >= 2) c.k_reg = std::min(opts->fusion, c.code_domain ? 7 : k_max), c.k_explicit = true;
         if (opts->max_ops > 0) c.max_ops = std::min(opts->max_ops, 256);
         if (opts->search == JQ_SEARCH_ON) c.search_rounds = 2;
         else if (opts->search == JQ_SEARCH_OFF) c.search_rounds = 0;

@@ -314,13 +314,16 @@ void upsert(std::vector<Entry>& v, const Entry& e) {
 jq_tuning default_tuning(int enc) {
     jq_tuning t{};
     // measured on an MI355X at N = 30 (see the planner's cost model):
-    // complex128 K = 4 (occupancy 4), complex64 K = 5; a pass streams in the
+    // complex128 K = 5, complex64 K = 6 (40 layers of Haar U(2) and CZ:
+    // 388 against 411 ms at K = 4, 222 against 226 ms at K = 5, the fused
+    // kernel compiled for the reduced op kinds; circuits with other gates
+    // plan at 4 and 5, PlanConfig::k_general_max); a pass streams in the
     // time of 19 (complex128) or 6 (complex64) ops; the per-gate kernels
     // take one pair per thread on every complex128 target (as fast or within
     // 2.5% everywhere, up to 12% faster from target 17 up), and four from
     // target 17 up for complex64, where the better width changes target by
     // target (the tuner chooses per target)
-    t.k_reg = enc == JQ_C64 ? 5 : 4;
+    t.k_reg = enc == JQ_C64 ? 6 : 5;
     t.pass_ops = enc == JQ_C64 ? 6.0 : 19.0;
     t.wide_mask = enc == JQ_C64 ? ~0ull << 17 : 0;
     t.wide_target = enc == JQ_C64 ? 17 : 64;

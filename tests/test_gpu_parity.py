@@ -267,7 +267,7 @@ def test_random_circuit_16_qubits(enc, fusion):
 
 @pytest.mark.parametrize("search", SEARCH)
 @pytest.mark.parametrize("enc", ["c128", "c64"])
-@pytest.mark.parametrize("n,fusion", [(10, 0), (13, 0), (17, 0), (17, 3), (18, 2), (19, 5)])
+@pytest.mark.parametrize("n,fusion", [(10, 0), (13, 0), (17, 0), (17, 3), (18, 2), (19, 5), (20, 6)])
 def test_layered_circuit_fused(enc, n, fusion, search):
     if enc == "c128" and fusion > 5:
         pytest.skip()

@@ -67,7 +67,11 @@ def test_autotune_measures_caches_and_matches_the_oracle(enc, _cache):
         s.apply_circuit(circ)
         assert O.rel_l2(s.amplitudes(), ref) <= TOL[enc] * 2
         steps = jq.plan_steps(n, enc, circ)
-        assert {st["k_reg"] for st in steps if st["fused"]} <= {t["k_reg"]}
+        # the random part holds CNOTs and controlled phases: the planner keeps
+        # such circuits at the widest width of 4 waves per SIMD for the kernel
+        # compiled for every op kind
+        cap = 5 if enc == "c64" else 4
+        assert {st["k_reg"] for st in steps if st["fused"]} <= {min(t["k_reg"], cap)}
 
 
 @pytest.mark.parametrize("enc", ["c128", "c64"])

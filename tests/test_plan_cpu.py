@@ -13,7 +13,9 @@ from paper_1805_04708_amd import jq
 from paper_1805_04708_amd import workloads as W
 
 # tile shape per encoding: fixed lane bits F, default register bits K
-LAYOUT = {"c128": (3, 4), "c64": (4, 5), "compact": (6, 4)}
+# (circuits with gates outside the reduced op kinds plan narrower:
+# complex128 4, complex64 5)
+LAYOUT = {"c128": (3, 5), "c64": (4, 6), "compact": (6, 4)}
 PER_BLOCK = jq.JQ_COMPACT_PER_BLOCK
 
 

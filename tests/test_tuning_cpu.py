@@ -34,7 +34,7 @@ def write(path, entries, version=1):
 
 def test_defaults_without_a_cache_file():
     # complex128: one pair per thread on every target; complex64: four from 17 up
-    for enc, k, ops, wide, mask in (("c128", 4, 19.0, 64, 0), ("c64", 5, 6.0, 17, (2**64 - 1) ^ (2**17 - 1))):
+    for enc, k, ops, wide, mask in (("c128", 5, 19.0, 64, 0), ("c64", 6, 6.0, 17, (2**64 - 1) ^ (2**17 - 1))):
         t = jq.tuning_get(30, enc)
         assert (t["k_reg"], t["pass_ops"], t["wide_target"], t["wide_mask"], t["source"]) == \
             (k, ops, wide, mask, "default")
@@ -108,11 +108,36 @@ def test_tuned_search_switch(_cache):
 
 def test_planner_uses_the_tuned_register_width():
     circ = W.layered_u2_cz(26, 2, seed=1)
-    assert {s["k_reg"] for s in jq.plan_steps(26, "c128", circ) if s["fused"]} == {4}
+    assert {s["k_reg"] for s in jq.plan_steps(26, "c128", circ) if s["fused"]} == {5}
     jq.tuning_set(26, "c128", k_reg=3)
     assert {s["k_reg"] for s in jq.plan_steps(26, "c128", circ) if s["fused"]} == {3}
     # an explicit fusion width in the options wins over the tuning
     assert {s["k_reg"] for s in jq.plan_steps(26, "c128", circ, fusion=5) if s["fused"]} == {5}
+
+
+def test_wide_register_width_only_for_reduced_kind_circuits():
+    # a width above the one where the fused kernel compiled for every op kind
+    # keeps 4 waves per SIMD (complex128 4, complex64 5) is kept only when
+    # every gate lowers to the reduced kinds (uncontrolled one-qubit dense
+    # gates, controlled Zs); a width asked for in the options is kept as given
+    n = 26
+    lite = W.layered_u2_cz(n, 2, seed=1)
+    with_cnot = lite + [("CNOT", (0, 9), ())]
+    with_rz = lite + [("RZ", (3,), (0.4,))]
+    with_ccz = lite + [("CZ", (1, 2), (), (3,))]  # a CZ with one more control
+    for enc, cap in (("c128", 4), ("c64", 5)):
+        def widths(c, **kw):
+            return {s["k_reg"] for s in jq.plan_steps(n, enc, c, **kw) if s["fused"]}
+        jq.tuning_set(n, enc, k_reg=cap + 1)
+        assert widths(lite) == {cap + 1}
+        assert widths(with_ccz) == {cap + 1}
+        assert widths(with_cnot) == {cap}
+        assert widths(with_rz) == {cap}
+        assert widths(with_cnot, fusion=cap + 1) == {cap + 1}
+        # at or below the limit the tuned width stands
+        jq.tuning_set(n, enc, k_reg=3)
+        assert widths(with_cnot) == {3}
+        jq.tuning_set(n, enc, clear=True)
 
 
 def test_autotune_needs_a_device():
