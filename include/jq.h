@@ -127,7 +127,12 @@ typedef struct {
  * choices the planner and the per-gate kernels make, and jq_autotune picks
  * them by timing them on the device:
  *  k_reg:       register bits of a fused tile pass (a lane holds 2^k_reg
- *               amplitudes): 2..5 for JQ_C128, 2..6 for JQ_C64;
+ *               amplitudes): 2..5 for JQ_C128, 2..6 for JQ_C64.  Unless
+ *               every gate of the circuit is an uncontrolled one-qubit
+ *               dense gate or a controlled Z, the planner uses at most 4
+ *               (JQ_C128) or 5 (JQ_C64), the widest at which the fused
+ *               kernel for the other op kinds keeps 4 waves per SIMD; a
+ *               width given in opts->fusion is used as given;
  *  pass_ops:    the planner's weight of one more pass against one more op
  *               in a pass (a pass's streaming time in units of one fused
  *               op's arithmetic), in (0, 10000];
