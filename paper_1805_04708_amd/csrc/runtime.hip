@@ -118,11 +118,16 @@ void drain_profile(jq_state* s) {
 //                        of fusable gates as a fused pass (results the same up
 //                        to rounding);
 //  JQ_ROCTX=1            roctx ranges around each call and each step, for
-//                        rocprofv3 --marker-trace.
+//                        rocprofv3 --marker-trace;
+//  JQ_FUSED_OPS=all      every complex128 / complex64 fused pass runs the op
+//                        loop compiled for every op kind, also where the
+//                        reduced loop would do (the same amplitudes, bit for
+//                        bit: both instances share the ops' code).
 struct DebugFlags {
     bool launch_blocking = false;
     int force = 0;  // 0: none, 1: per gate, 2: fused
     bool roctx = false;
+    bool fused_all_kinds = false;
 };
 
 const DebugFlags& debug_flags() {
@@ -135,6 +140,7 @@ const DebugFlags& debug_flags() {
             if (!std::strcmp(k, "per_gate")) d.force = 1;
             else if (!std::strcmp(k, "fused")) d.force = 2;
         }
+        if (const char* k = std::getenv("JQ_FUSED_OPS")) d.fused_all_kinds = !std::strcmp(k, "all");
         return d;
     }();
     return f;
@@ -417,6 +423,7 @@ void run_step(jq_state* s, const std::vector<GateOp>& ops, const PlanConfig& cfg
     }
     {
         Timed t(s, K_FUSED, 2.0 * sweep);
+        if (debug_flags().fused_all_kinds) p.kinds = 0;  // kinds not recorded: the general loop
         sv_apply_fused(s->enc, s->buf, s->n, p, step.k_reg, cfg.fixed_lane_bits, s->stream);
     }
     blocking_check(s, "fused pass");

@@ -614,3 +614,45 @@ def test_debug_switches_keep_oracle_parity(force):
     r = subprocess.run([sys.executable, "-c", GPU_SNIPPET.format(root=root)], env=env, capture_output=True,
                        text=True, timeout=240)
     assert r.returncode == 0 and "switches ok" in r.stdout, r.stderr[-3000:]
+
+
+LOOP_SNIPPET = """
+import hashlib, sys
+sys.path.insert(0, {root!r})
+import torch
+from paper_1805_04708_amd import jq, workloads as W
+torch.cuda.set_device(0)
+cases = {cases!r}
+out = []
+for enc, n, k in cases:
+    with jq.State(n, enc) as s:
+        s.apply_circuit(W.layered_u2_cz(n, 6, seed=n + k), fusion=k)
+        out.append(hashlib.sha256(s.amplitudes().tobytes()).hexdigest())
+print("hashes " + " ".join(out))
+"""
+
+
+def test_reduced_op_loop_matches_the_general_loop_bit_for_bit():
+    # layered U(2) + CZ circuits lower to dense and multiplexed 2x2s and
+    # negations only, so every pass runs the op loop compiled for those
+    # kinds; JQ_FUSED_OPS=all (read once per process: a child) runs the same
+    # plans with the loop compiled for every kind.  Both share the ops' code,
+    # so the amplitudes agree bit for bit.
+    import hashlib
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cases = [("c128", 16, 4), ("c128", 16, 5), ("c64", 16, 5), ("c64", 17, 6)]
+    here = []
+    for enc, n, k in cases:
+        with jq.State(n, enc) as s:
+            s.apply_circuit(W.layered_u2_cz(n, 6, seed=n + k), fusion=k)
+            here.append(hashlib.sha256(s.amplitudes().tobytes()).hexdigest())
+    env = dict(os.environ, JQ_FUSED_OPS="all")
+    print("child with JQ_FUSED_OPS=all", flush=True)
+    r = subprocess.run([sys.executable, "-c", LOOP_SNIPPET.format(root=root, cases=cases)], env=env,
+                       capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-3000:]
+    line = [x for x in r.stdout.splitlines() if x.startswith("hashes ")][-1]
+    assert line.split()[1:] == here
