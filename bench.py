@@ -213,7 +213,7 @@ def cpu_baseline(n, circuit, gates, batch_states=None, batch_count=CPU_BATCH_SAM
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU path.",
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np

@@ -50,7 +50,7 @@ extern "C" {
 #define JQ_EINVAL (-1)       /* invalid argument */
 #define JQ_ENOMEM (-2)       /* not enough device (HBM) memory */
 #define JQ_EDEVICE (-3)      /* HIP runtime error or device fault */
-#define JQ_EUNSUPPORTED (-4) /* valid request this build does not implement */
+#define JQ_EUNSUPPORTED (-4) /* a valid request the library does not implement */
 #define JQ_EZERO (-5)        /* projection onto a zero-probability outcome */
 #define JQ_EBUSY (-6)        /* server queue full (non-blocking submit) */
 
