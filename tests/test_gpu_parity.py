@@ -136,6 +136,30 @@ def test_every_gate_class_every_target(enc, n):
 
 
 @pytest.mark.parametrize("enc", ["c128", "c64"])
+@pytest.mark.parametrize("n", [8, 9, 12])
+def test_two_qubit_dense_gates_on_low_qubits(enc, n):
+    # every ordered pair with a qubit below 4: from N = 9 up the uncontrolled
+    # ones whose lower qubit lies inside a 128-byte line (below 3 for
+    # complex128, 4 for complex64) run the lane-exchange kernel (whole chunks
+    # of 256 pairs), the others and all at N = 8 the four-amplitude kernel;
+    # controlled ones always run the latter
+    rng = np.random.default_rng(700 + n)
+    psi0 = rand_state(rng, n)
+    circ = []
+    for a in range(n):
+        for b in range(n):
+            if a != b and min(a, b) < 4:
+                circ.append(("MAT2", (a, b), random_u4(rng)))
+    got = run_gpu(n, enc, circ, fusion=1, init=psi0)
+    ref = run_oracle(n, circ, init=psi0)
+    assert O.rel_l2(got, ref) <= tol(enc, len(circ)), O.rel_l2(got, ref)
+    ctrl = [("MAT2", (0, 1), random_u4(rng), (5,)), ("MAT2", (2, 0), random_u4(rng), (4, 7))]
+    got = run_gpu(n, enc, ctrl, fusion=1, init=psi0)
+    ref = run_oracle(n, ctrl, init=psi0)
+    assert O.rel_l2(got, ref) <= tol(enc, len(ctrl)), O.rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
 def test_apply_gate_entry_point(enc):
     n = 9
     rng = np.random.default_rng(5)
