@@ -136,6 +136,29 @@ def test_every_gate_class_every_target(enc, n):
 
 
 @pytest.mark.parametrize("enc", ["c128", "c64"])
+def test_reduced_kind_circuit_at_the_default_width(enc):
+    # uncontrolled one-qubit dense gates and controlled Zs (with up to two
+    # more controls) plan at the default width (2^5 register slots for
+    # complex128, 2^6 for complex64) and run the reduced op loop, negations
+    # with register and thread controls included
+    n = 14
+    rng = np.random.default_rng(31)
+    circ = []
+    for _ in range(6):
+        circ += [("MAT1", (q,), W.haar_u2(rng)) for q in range(n)]
+        for _ in range(5):
+            a, b, c, d = (int(x) for x in rng.permutation(n)[:4])
+            k = int(rng.integers(0, 3))
+            circ.append(("CZ", (a, b), (), (c, d)[:k]) if k else ("CZ", (a, b), ()))
+    k_want = 6 if enc == "c64" else 5
+    assert {st["k_reg"] for st in jq.plan_steps(n, enc, circ) if st["fused"]} == {k_want}
+    psi0 = rand_state(rng, n)
+    got = run_gpu(n, enc, circ, init=psi0)
+    ref = run_oracle(n, circ, init=psi0)
+    assert O.rel_l2(got, ref) <= tol(enc, len(circ)), O.rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("enc", ["c128", "c64"])
 @pytest.mark.parametrize("n", [8, 9, 12])
 def test_two_qubit_dense_gates_on_low_qubits(enc, n):
     # every ordered pair with a qubit below 4: from N = 9 up the uncontrolled
