@@ -305,3 +305,41 @@ def test_n34_per_gate_kernels_on_the_full_grid():
             want *= -1j * r2 * math.sin(psi / 2) if b[2] else r2 * math.cos(psi / 2)
             assert abs(s.amplitudes(i, 1)[0] - want) < 1e-15, i
         assert abs(s.norm() - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("enc,tol", [("c128", 1e-15), ("c64", 2e-7)])
+def test_n30_two_qubit_gates_on_low_qubits_closed_form(enc, tol):
+    # two-qubit dense gates on disjoint pairs of a uniform 30-qubit state,
+    # whose lower qubit lies inside a 128-byte line (the lane-exchange kernel
+    # for complex128 pairs (0, 1) and (5, 2), complex64 also (4, 3)): the
+    # state stays a product over the pairs, each amplitude the uniform
+    # amplitude times one row sum of each matrix
+    n = 30
+    if free_gib() < 17:
+        pytest.skip("needs 16 GiB of free HBM")
+    rng = np.random.default_rng(30)
+    pairs = [(0, 1), (5, 2), (4, 3), (20, 9)]
+    mats = []
+    for _ in pairs:
+        q, _r = np.linalg.qr(rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4)))
+        mats.append(q)
+    circ = []
+    for (a, b), m in zip(pairs, mats):
+        flat = np.empty(32)
+        flat[0::2], flat[1::2] = m.real.ravel(), m.imag.ravel()
+        circ.append(("MAT2", (a, b), tuple(flat)))
+    amp = 2.0 ** (-n / 2)
+    with jq.State(n, enc) as s:
+        s.init(jq.JQ_INIT_UNIFORM)
+        s.apply_circuit(circ, fusion=1)
+        idx = [0, 1, 2, 3, 0b111111, (1 << n) - 1, 987654321] + [int(x) for x in rng.integers(0, 1 << n, 40)]
+        for i in idx:
+            want, scale = amp, amp
+            for (a, b), m in zip(pairs, mats):
+                # the first-listed qubit is the most significant bit of the row
+                row = m[2 * ((i >> a) & 1) + ((i >> b) & 1)]
+                want *= row.sum()
+                scale *= np.abs(row).sum()
+            # each gate's rounding is relative to its terms, not its sum
+            assert abs(s.amplitudes(i, 1)[0] - want) <= 8 * len(pairs) * tol * scale, (i, enc)
+        assert abs(s.norm() - 1.0) < (1e-12 if enc == "c128" else 1e-5)
