@@ -286,13 +286,19 @@ def test_n34_per_gate_kernels_on_the_full_grid():
     with jq.State(n, "c128") as s:
         s.init(jq.JQ_INIT_UNIFORM)
         theta, phi, psi = 0.8, 0.3, 1.1
-        # qubits 0-2 take the lane-exchange kernels (dense and X), whose
-        # capped grid loops 16 times over the 2^26 chunks of 256 amplitudes
+        m2 = np.linalg.qr(np.random.default_rng(34).normal(size=(4, 4))
+                          + 1j * np.random.default_rng(35).normal(size=(4, 4)))[0]
+        flat = np.empty(32)
+        flat[0::2], flat[1::2] = m2.real.ravel(), m2.imag.ravel()
+        # qubits 0-2 take the lane-exchange kernels (dense, X and the
+        # two-qubit gate on (1, 3)), whose capped grids loop over the 2^26
+        # chunks of 256 amplitudes (2^25 of 256 pairs)
         s.apply_circuit([("RZ", (5,), (theta,)), ("CNOT", (3, 33), ()), ("H", (7,), ()),
                          ("RZ", (1,), (phi,)), ("X", (1,), ()), ("RZ", (2,), (psi,)), ("H", (2,), ()),
-                         ("H", (0,), ())], fusion=1)
+                         ("H", (0,), ()), ("MAT2", (1, 3), tuple(flat))], fusion=1)
         amp = 2.0 ** (-n / 2)
         r2 = math.sqrt(2)
+        f1 = [np.exp(0.5j * phi), np.exp(-0.5j * phi)]  # qubit 1 after RZ and X
         for i in [0, 1 << 5, 2, 4, 6, 0b100110, (1 << n) - 1, (1 << n) - 1 - 0b10000001, 987654321, 987654320]:
             b = [(i >> q) & 1 for q in range(8)]
             # the state stays a product over qubits: CNOT(3, 33) leaves a
@@ -301,8 +307,10 @@ def test_n34_per_gate_kernels_on_the_full_grid():
             want *= np.exp(0.5j * theta) if b[5] else np.exp(-0.5j * theta)
             want *= 0.0 if b[7] else r2  # H on a uniform qubit
             want *= 0.0 if b[0] else r2
-            want *= np.exp(-0.5j * phi) if b[1] else np.exp(0.5j * phi)  # X swaps the RZ phases
             want *= -1j * r2 * math.sin(psi / 2) if b[2] else r2 * math.cos(psi / 2)
+            # the two-qubit gate on (1, 3) (qubit 1 the row's most significant
+            # bit) mixes qubit 1's phases, qubit 3 still uniform
+            want *= sum(m2[2 * b[1] + ((i >> 3) & 1), c] * f1[c >> 1] for c in range(4))
             assert abs(s.amplitudes(i, 1)[0] - want) < 1e-15, i
         assert abs(s.norm() - 1.0) < 1e-12
 
